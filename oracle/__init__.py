@@ -1,0 +1,8 @@
+"""Serial FP64 CPU oracle for the RKL2 conduction super-step.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg may use this package; the product path never does.
+"""
+from .oracle import (  # noqa: F401
+    Grid, build, load, mc, stages, coeffs, dt_par, flux_div, rkl2_fixed, superstep,
+)

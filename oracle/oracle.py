@@ -1,0 +1,181 @@
+"""ctypes front end of the serial FP64 oracle (``rkl_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  This module compiles and calls the plain C oracle;
+it shares nothing with the HIP library and imports nothing from it.  Arrays
+are numpy float64, C-contiguous, layout [n2][n1][n0] (axis 0 fastest); ``b``
+is shaped (3, n2, n1, n0).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rkl_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class _CGrid(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("h", ctypes.c_double * 3),
+        ("limiter", ctypes.c_int),
+        ("saturation", ctypes.c_int),
+        ("phi", ctypes.c_double),
+        ("kappa0", ctypes.c_double),
+        ("kappa_exp", ctypes.c_double),
+        ("kperp_ratio", ctypes.c_double),
+        ("rho", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("cp", ctypes.c_double),
+    ]
+
+
+@dataclass
+class Grid:
+    """Periodic grid + conduction parameters (same meaning as in rkl_oracle.c)."""
+    n: tuple                      # (n0, n1, n2), axis 0 fastest
+    h: tuple = (1.0, 1.0, 1.0)
+    ndim: int = 3
+    limiter: int = 0
+    saturation: int = 0
+    phi: float = 0.3
+    kappa0: float = 1.0
+    kappa_exp: float = 0.0
+    kperp_ratio: float = 0.0
+    rho: float = 1.0
+    gamma: float = 2.0
+    cp: float = 0.5
+    _c: _CGrid = field(default=None, repr=False, compare=False)
+
+    @property
+    def shape(self):
+        return (self.n[2], self.n[1], self.n[0])
+
+    def c(self) -> _CGrid:
+        g = _CGrid()
+        g.ndim = int(self.ndim)
+        for d in range(3):
+            g.n[d] = int(self.n[d])
+            g.h[d] = float(self.h[d])
+        g.limiter = int(self.limiter)
+        g.saturation = int(self.saturation)
+        g.phi = float(self.phi)
+        g.kappa0 = float(self.kappa0)
+        g.kappa_exp = float(self.kappa_exp)
+        g.kperp_ratio = float(self.kperp_ratio)
+        g.rho = float(self.rho)
+        g.gamma = float(self.gamma)
+        g.cp = float(self.cp)
+        return g
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math)."""
+    stale = (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+    if force or stale:
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+            "-fPIC", "-shared", "-o", tmp, _SRC, "-lm",
+        ])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        dp = ctypes.POINTER(ctypes.c_double)
+        gp = ctypes.POINTER(_CGrid)
+        lib.orc_mc.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_mc.restype = ctypes.c_double
+        lib.orc_stages.argtypes = [ctypes.c_double]
+        lib.orc_stages.restype = ctypes.c_int
+        lib.orc_coeffs.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
+        lib.orc_coeffs.restype = None
+        lib.orc_dt_par.argtypes = [gp, dp]
+        lib.orc_dt_par.restype = ctypes.c_double
+        lib.orc_flux_div.argtypes = [gp, dp, dp, dp]
+        lib.orc_flux_div.restype = None
+        lib.orc_rkl2_fixed.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double]
+        lib.orc_rkl2_fixed.restype = None
+        lib.orc_superstep.argtypes = [gp, dp, dp, ctypes.c_double, dp]
+        lib.orc_superstep.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _field(g: Grid, a, name):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != g.shape:
+        raise ValueError(f"{name}: shape {a.shape} != {g.shape}")
+    return a
+
+
+def _bfield(g: Grid, b):
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    if b.shape != (3,) + g.shape:
+        raise ValueError(f"b: shape {b.shape} != {(3,) + g.shape}")
+    return b
+
+
+def mc(a: float, b: float) -> float:
+    return load().orc_mc(a, b)
+
+
+def stages(r: float) -> int:
+    return load().orc_stages(r)
+
+
+def coeffs(s: int):
+    """(w1, mu, nu, mut, gt) with arrays indexed by stage j = 0..s."""
+    arrs = [np.zeros(s + 1) for _ in range(4)]
+    w1 = ctypes.c_double()
+    load().orc_coeffs(s, ctypes.byref(w1), *[_ptr(a) for a in arrs])
+    return (w1.value, *arrs)
+
+
+def dt_par(g: Grid, T) -> float:
+    T = _field(g, T, "T")
+    cg = g.c()
+    return load().orc_dt_par(ctypes.byref(cg), _ptr(T))
+
+
+def flux_div(g: Grid, T, b) -> np.ndarray:
+    T = _field(g, T, "T")
+    b = _bfield(g, b)
+    out = np.empty(g.shape)
+    cg = g.c()
+    load().orc_flux_div(ctypes.byref(cg), _ptr(T), _ptr(b), _ptr(out))
+    return out
+
+
+def rkl2_fixed(g: Grid, T, b, s: int, tau: float) -> np.ndarray:
+    """s RKL2 stages of length tau; returns Y_s (input is not modified)."""
+    T = _field(g, T, "T").copy()
+    b = _bfield(g, b)
+    cg = g.c()
+    load().orc_rkl2_fixed(ctypes.byref(cg), _ptr(T), _ptr(b), int(s), float(tau))
+    return T
+
+
+def superstep(g: Grid, T, b, dt_hyp: float):
+    """One super-step; returns (T_new, s, dt_par)."""
+    T = _field(g, T, "T").copy()
+    b = _bfield(g, b)
+    cg = g.c()
+    dtp = ctypes.c_double()
+    s = load().orc_superstep(ctypes.byref(cg), _ptr(T), _ptr(b), float(dt_hyp), ctypes.byref(dtp))
+    return T, s, dtp.value

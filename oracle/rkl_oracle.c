@@ -1,0 +1,299 @@
+/*
+ * rkl_oracle.c -- serial FP64 reference for one RKL2 super-step of
+ * field-aligned (anisotropic) thermal conduction.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker that the HIP path is
+ * compared against.  Only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it; the product path never does.  It shares no
+ * code, header, table or helper with the HIP library.
+ *
+ * Source: Vaidya, Prasad, Mignone, Sharma & Rickler (2017), "Scalable explicit
+ * implementation of anisotropic diffusion with Runge-Kutta-Legendre
+ * super-time-stepping" (arXiv:1702.05487).
+ *
+ * What is computed (all FP64, no blocking, no fusion):
+ *   - the conductive flux at every cell face: harmonic blend of the classical
+ *     field-aligned flux and the saturated flux (Sec. 2, Eqs. Fc, Fclass,
+ *     Fsat; the perpendicular term that Sec. 2 calls straightforward to add),
+ *     with the transverse temperature gradients either averaged or limited
+ *     with the monotonized-central limiter (Sec. 3.4 and Appendix B);
+ *   - the conservative second-order divergence of that flux (Sec. 3, the
+ *     finite-difference formula under Eq. scalar_diffusion);
+ *   - the explicit parabolic step (Sec. 3.1, Eq. dt_exp, HD diffusivity);
+ *   - the number of RKL2 stages from the super-step (Sec. 3.3, Eq. RKL-s,
+ *     rounded up as stated at the start of Sec. 4.1);
+ *   - the RKL2 coefficients and stage scheme (Appendix A, Eq. rkl2scheme and
+ *     the coefficient formulas that follow it).
+ *
+ * Readings where the paper is silent (each listed in the design notes):
+ *   face temperature = mean of the two cells; conductivities and the
+ *   saturated flux use max(T_face, 0); the face field direction is the
+ *   normalised sum of the two cell unit vectors (zero when that sum is
+ *   shorter than 1e-12); the limited transverse gradient at a face is
+ *   MC(MC(a1,a2), MC(a3,a4)) over the one-sided differences of the two cells,
+ *   the unlimited one is their mean; the saturated flux is central, with the
+ *   full face flux vector's magnitude in the harmonic blend; c_iso = sqrt(T)
+ *   (p = rho T in code units); the stage operator is evaluated on each
+ *   stage's own temperature and tau*M(Y0) is computed once and reused;
+ *   boundaries are periodic.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math), so every
+ * a*b+c rounds twice, exactly as written.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Grid and physics parameters.  Layout of every field: [n2][n1][n0], axis 0
+ * fastest.  b is three such arrays back to back (component-major). */
+typedef struct {
+    int ndim;           /* 1, 2 or 3; axes >= ndim must have n = 1 */
+    int n[3];           /* cells per axis */
+    double h[3];        /* cell widths */
+    int limiter;        /* 0: mean of the four one-sided differences, 1: MC */
+    int saturation;     /* 0: classical flux only, 1: harmonic blend with q */
+    double phi;         /* saturation uncertainty factor (Eq. Fsat) */
+    double kappa0;      /* kappa_par = kappa0 * T^kappa_exp */
+    double kappa_exp;
+    double kperp_ratio; /* kappa_perp = kperp_ratio * kappa_par */
+    double rho;         /* frozen density */
+    double gamma;       /* ratio of specific heats */
+    double cp;          /* parabolic Courant number, <= 1/2 */
+} orc_grid;
+
+static long ncell(const orc_grid *g) { return (long)g->n[0] * g->n[1] * g->n[2]; }
+
+/* periodic index of cell (c[0], c[1], c[2]) */
+static long cell_index(const orc_grid *g, const int c[3])
+{
+    int w[3];
+    for (int d = 0; d < 3; ++d) {
+        int m = c[d] % g->n[d];
+        w[d] = m < 0 ? m + g->n[d] : m;
+    }
+    return ((long)w[2] * g->n[1] + w[1]) * g->n[0] + w[0];
+}
+
+static double value_at(const orc_grid *g, const double *f, const int c[3], int d, int shift)
+{
+    int q[3] = {c[0], c[1], c[2]};
+    q[d] += shift;
+    return f[cell_index(g, q)];
+}
+
+/* Parallel conductivity kappa0 * T^kappa_exp with T clipped at zero. */
+static double kappa_par(const orc_grid *g, double T)
+{
+    double t = T > 0.0 ? T : 0.0;
+    if (g->kappa_exp == 0.0) return g->kappa0;
+    if (g->kappa_exp == 2.5) return g->kappa0 * (t * t * sqrt(t));
+    return g->kappa0 * pow(t, g->kappa_exp);
+}
+
+/* Monotonized-central limiter of two slopes: minmod(2a, 2b, (a+b)/2). */
+double orc_mc(double a, double b)
+{
+    if (a * b <= 0.0) return 0.0;
+    double m = fabs(a + b) * 0.5;
+    double ta = 2.0 * fabs(a), tb = 2.0 * fabs(b);
+    if (ta < m) m = ta;
+    if (tb < m) m = tb;
+    return a > 0.0 ? m : -m;
+}
+
+/*
+ * Component d of the conductive flux through the face between cell c and its
+ * +e_d neighbour (Eqs. Fc, Fclass, Fsat plus the perpendicular term).
+ */
+static double face_flux(const orc_grid *g, const double *T, const double *b,
+                        const int c[3], int d)
+{
+    const long N = ncell(g);
+    int r[3] = {c[0], c[1], c[2]};
+    r[d] += 1;
+    const long iL = cell_index(g, c), iR = cell_index(g, r);
+    const double TL = T[iL], TR = T[iR];
+
+    /* temperature and conductivities at the face */
+    const double Tf = 0.5 * (TL + TR);
+    const double kpar = kappa_par(g, Tf);
+    const double kperp = g->kperp_ratio * kpar;
+
+    /* field direction at the face */
+    double bf[3], nb2 = 0.0;
+    for (int e = 0; e < 3; ++e) {
+        bf[e] = b[e * N + iL] + b[e * N + iR];
+        nb2 += bf[e] * bf[e];
+    }
+    const double nb = sqrt(nb2);
+    for (int e = 0; e < 3; ++e) bf[e] = nb < 1e-12 ? 0.0 : bf[e] / nb;
+
+    /* temperature gradient at the face: normal component is face-native,
+     * the two transverse components come from one-sided differences in the
+     * two cells that share the face (Appendix B) */
+    double G[3];
+    for (int e = 0; e < 3; ++e) {
+        if (e == d) {
+            G[e] = (TR - TL) / g->h[d];
+            continue;
+        }
+        const double he = g->h[e];
+        double a1 = (TL - value_at(g, T, c, e, -1)) / he;
+        double a2 = (value_at(g, T, c, e, +1) - TL) / he;
+        double a3 = (TR - value_at(g, T, r, e, -1)) / he;
+        double a4 = (value_at(g, T, r, e, +1) - TR) / he;
+        if (g->limiter)
+            G[e] = orc_mc(orc_mc(a1, a2), orc_mc(a3, a4));
+        else
+            G[e] = 0.25 * (a1 + a2 + a3 + a4);
+    }
+
+    /* classical flux vector  F = -[kperp G + (kpar - kperp) b (b.G)] */
+    const double bG = bf[0] * G[0] + bf[1] * G[1] + bf[2] * G[2];
+    double F[3];
+    for (int e = 0; e < 3; ++e)
+        F[e] = -(kperp * G[e] + (kpar - kperp) * bf[e] * bG);
+
+    if (!g->saturation) return F[d];
+
+    /* saturated flux q = 5 phi rho c_iso^3 with c_iso = sqrt(T), blended
+     * harmonically with the magnitude of the classical flux (Eq. Fc) */
+    const double t = Tf > 0.0 ? Tf : 0.0;
+    const double q = 5.0 * g->phi * g->rho * (t * sqrt(t));
+    const double Fm = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+    if (q == 0.0) return 0.0;
+    return q / (q + Fm) * F[d];
+}
+
+/*
+ * out = (gamma-1)/rho * ( -div F_c(T) ), the conservative second-order
+ * difference of the face fluxes (Sec. 3).  With rho*eps = rho T/(gamma-1)
+ * this is dT/dt of Eq. scalar_diffusion.
+ */
+void orc_flux_div(const orc_grid *g, const double *T, const double *b, double *out)
+{
+    const double fac = (g->gamma - 1.0) / g->rho;
+    for (int k = 0; k < g->n[2]; ++k)
+        for (int j = 0; j < g->n[1]; ++j)
+            for (int i = 0; i < g->n[0]; ++i) {
+                const int c[3] = {i, j, k};
+                double div = 0.0;
+                for (int d = 0; d < g->ndim; ++d) {
+                    int l[3] = {i, j, k};
+                    l[d] -= 1;
+                    const double Fp = face_flux(g, T, b, c, d);
+                    const double Fm = face_flux(g, T, b, l, d);
+                    div += (Fp - Fm) / g->h[d];
+                }
+                out[cell_index(g, c)] = fac * (-div);
+            }
+}
+
+/*
+ * Explicit parabolic step (Eq. dt_exp) with the HD diffusivity
+ * chi = kappa_par (gamma-1)/rho in every direction, maximised over cells.
+ * Returns +inf when the maximum is zero.
+ */
+double orc_dt_par(const orc_grid *g, const double *T)
+{
+    double inv_h2 = 0.0;
+    for (int d = 0; d < g->ndim; ++d) inv_h2 += 1.0 / (g->h[d] * g->h[d]);
+    const double fac = (g->gamma - 1.0) / g->rho;
+    double lam = 0.0;
+    const long N = ncell(g);
+    for (long i = 0; i < N; ++i) {
+        const double v = fac * kappa_par(g, T[i]) * inv_h2;
+        if (v > lam) lam = v;
+    }
+    if (lam == 0.0) return INFINITY;
+    return g->cp / lam;
+}
+
+/*
+ * Number of RKL2 stages for r = dt_hyp/dt_par: the real root of
+ * r = (s^2 + s - 2)/4 (Eq. RKL-s), then s -> 1 + floor(s) (Sec. 4.1).
+ */
+int orc_stages(double r)
+{
+    const double s_real = (-1.0 + sqrt(9.0 + 16.0 * r)) / 2.0;
+    return 1 + (int)floor(s_real);
+}
+
+/*
+ * RKL2 coefficients for an s-stage super-step (Appendix A).  Arrays are
+ * indexed by stage j = 0..s; entries that the scheme does not use are 0.
+ *   b_j = (j^2+j-2)/(2j(j+1)) for j > 2, b_0 = b_1 = b_2 = 1/3, a_j = 1 - b_j
+ *   w1 = 4/(s^2+s-2)
+ *   mut_1 = b_1 w1
+ *   mu_j = (2j-1)/j * b_j/b_{j-1},  nu_j = -(j-1)/j * b_j/b_{j-2}
+ *   mut_j = mu_j w1,  gt_j = -a_{j-1} mut_j          (2 <= j <= s)
+ */
+void orc_coeffs(int s, double *w1_out, double *mu, double *nu, double *mut, double *gt)
+{
+    double *bj = (double *)malloc(sizeof(double) * (s + 1));
+    for (int j = 0; j <= s; ++j) {
+        if (j <= 2) bj[j] = 1.0 / 3.0;
+        else bj[j] = ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
+    }
+    const double w1 = 4.0 / ((double)s * s + s - 2.0);
+    for (int j = 0; j <= s; ++j) mu[j] = nu[j] = mut[j] = gt[j] = 0.0;
+    mut[1] = bj[1] * w1;
+    for (int j = 2; j <= s; ++j) {
+        mu[j] = (2.0 * j - 1.0) / j * bj[j] / bj[j - 1];
+        nu[j] = -(j - 1.0) / j * bj[j] / bj[j - 2];
+        mut[j] = mu[j] * w1;
+        gt[j] = -(1.0 - bj[j - 1]) * mut[j];
+    }
+    *w1_out = w1;
+    free(bj);
+}
+
+/*
+ * s stages of RKL2 over a super-step tau (Eq. rkl2scheme); T holds Y_0 on
+ * entry and Y_s on return.  M is the flux-divergence operator above,
+ * evaluated on each stage's own temperature.
+ */
+void orc_rkl2_fixed(const orc_grid *g, double *T, const double *b, int s, double tau)
+{
+    const long N = ncell(g);
+    double *mu = malloc(sizeof(double) * (s + 1)), *nu = malloc(sizeof(double) * (s + 1));
+    double *mut = malloc(sizeof(double) * (s + 1)), *gt = malloc(sizeof(double) * (s + 1));
+    double w1;
+    orc_coeffs(s, &w1, mu, nu, mut, gt);
+
+    double *Y0 = malloc(sizeof(double) * N), *MY0 = malloc(sizeof(double) * N);
+    double *Yjm2 = malloc(sizeof(double) * N), *Yjm1 = malloc(sizeof(double) * N);
+    double *Yj = malloc(sizeof(double) * N), *L = malloc(sizeof(double) * N);
+
+    memcpy(Y0, T, sizeof(double) * N);
+    orc_flux_div(g, Y0, b, L);
+    for (long i = 0; i < N; ++i) MY0[i] = tau * L[i];
+    for (long i = 0; i < N; ++i) Yjm1[i] = Y0[i] + mut[1] * MY0[i];
+    memcpy(Yjm2, Y0, sizeof(double) * N);
+
+    for (int j = 2; j <= s; ++j) {
+        orc_flux_div(g, Yjm1, b, L);
+        for (long i = 0; i < N; ++i)
+            Yj[i] = mu[j] * Yjm1[i] + nu[j] * Yjm2[i] + (1.0 - mu[j] - nu[j]) * Y0[i]
+                  + mut[j] * tau * L[i] + gt[j] * MY0[i];
+        double *t = Yjm2; Yjm2 = Yjm1; Yjm1 = Yj; Yj = t;
+    }
+    memcpy(T, Yjm1, sizeof(double) * N);
+
+    free(mu); free(nu); free(mut); free(gt);
+    free(Y0); free(MY0); free(Yjm2); free(Yjm1); free(Yj); free(L);
+}
+
+/*
+ * One RKL2 super-step of length dt_hyp: dt_par from T, s from the ratio,
+ * then the stages.  Returns s; *dt_par_out receives dt_par.
+ */
+int orc_superstep(const orc_grid *g, double *T, const double *b, double dt_hyp, double *dt_par_out)
+{
+    const double dtp = orc_dt_par(g, T);
+    const double r = isinf(dtp) ? 0.0 : dt_hyp / dtp;
+    const int s = orc_stages(r);
+    if (dt_par_out) *dt_par_out = dtp;
+    orc_rkl2_fixed(g, T, b, s, dt_hyp);
+    return s;
+}
