@@ -1,0 +1,198 @@
+/*
+ * rkl.h -- C ABI of librkl: RKL2 super-time-stepping of field-aligned
+ * (anisotropic) thermal conduction on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Vaidya, Prasad, Mignone, Sharma & Rickler (2017), "Scalable
+ * explicit implementation of anisotropic diffusion with Runge-Kutta-Legendre
+ * super-time-stepping", arXiv:1702.05487.
+ *
+ * The library evolves a cell-centred temperature T under the operator-split
+ * conduction equation d(rho eps)/dt = -div F_c (Sec. 3, Eq. scalar_diffusion)
+ * with rho eps = rho T/(gamma-1), i.e. dT/dt = (gamma-1)/rho (-div F_c),
+ * on periodic Cartesian grids.  F_c is the harmonic blend of the classical
+ * field-aligned flux -kappa_par b (b.grad T) (plus an optional
+ * -kappa_perp (grad T - b (b.grad T)) term) and the saturated flux
+ * q = 5 phi rho c_iso^3 (Sec. 2, Eqs. Fc, Fclass, Fsat), discretised with
+ * the conservative second-order face differences of Sec. 3 and, optionally,
+ * monotonized-central limited transverse gradients (Sec. 3.4, Appendix B).
+ * A super-step of length dt_hyp takes s RKL2 stages (Appendix A, Eq.
+ * rkl2scheme), s from Eq. RKL-s rounded as 1 + floor(s) (Sec. 4.1), with the
+ * explicit step dt_par of Eq. dt_exp.
+ *
+ * Conventions common to every entry point:
+ *   - Fields are device pointers, C order [n2][n1][n0] (axis 0 fastest).
+ *     T is double.  b (the unit vector b = B/|B|, one per cell) is three such
+ *     arrays back to back (component-major, 3*N elements); it is double for
+ *     RKL_FP64 plans and float for RKL_MIXED plans.
+ *   - The caller owns every pointer it passes; the plan owns its scratch.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued on it; entry points that must read a device result back say
+ *     so and synchronise that stream.
+ *   - Every entry point returns an rkl_status; nothing aborts and no C++
+ *     exception crosses the ABI.  rkl_last_error() gives a message for the
+ *     calling thread's last non-OK status.
+ *   - One plan must not be used from two streams or threads at once.
+ */
+#ifndef RKL_H
+#define RKL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rkl_plan_s *rkl_plan_t;
+
+typedef enum {
+    RKL_OK = 0,
+    RKL_EINVAL = 1,     /* invalid argument or descriptor */
+    RKL_ENOMEM = 2,     /* device allocation failed */
+    RKL_EDEVICE = 3,    /* HIP runtime error (launch, copy, sync) */
+    RKL_ESTAGES = 4,    /* stage count above the plan's smax; T left unchanged */
+    RKL_ESTATE = 5      /* call out of order (e.g. launch before capture) */
+} rkl_status;
+
+enum { RKL_FP64 = 0, RKL_MIXED = 1 };   /* flux arithmetic: FP64, or FP32 with FP64 stage recurrence */
+enum { RKL_LIM_NONE = 0, RKL_LIM_MC = 1 };
+
+/* flag bits reported by rkl_query */
+enum {
+    RKL_FLAG_NONPOS = 1u,     /* some input temperature <= 0 (conductivity clipped at 0) */
+    RKL_FLAG_NONFINITE = 2u,  /* some input temperature is NaN or infinite */
+    RKL_FLAG_STAGES = 4u      /* the stage count exceeded smax; that grid was not advanced */
+};
+
+/* One periodic grid and its conduction parameters. */
+typedef struct {
+    int32_t ndim;         /* 1, 2 or 3; n[d] must be 1 for d >= ndim */
+    int32_t n[3];         /* cells along axes 0, 1, 2 (axis 0 fastest in memory) */
+    double h[3];          /* cell widths, > 0 */
+    int32_t limiter;      /* RKL_LIM_NONE: transverse gradient = mean of the four
+                             one-sided differences; RKL_LIM_MC: MC(MC(a1,a2), MC(a3,a4)) */
+    int32_t saturation;   /* 0: classical flux; 1: blend q/(q+|F|) F (Eq. Fc) */
+    double phi;           /* saturation factor of Eq. Fsat (0.3 in the paper) */
+    double kappa0;        /* kappa_par = kappa0 * max(T,0)^kappa_exp, kappa0 >= 0 */
+    double kappa_exp;     /* >= 0 (2.5 for Spitzer conduction) */
+    double kperp_ratio;   /* kappa_perp = kperp_ratio * kappa_par, in [0, 1] */
+    double rho;           /* frozen density, > 0 */
+    double gamma;         /* ratio of specific heats, > 1 */
+    double cp;            /* parabolic Courant number of Eq. dt_exp, in (0, 1/2] */
+} rkl_grid_desc;
+
+typedef struct {
+    int32_t precision;    /* RKL_FP64 or RKL_MIXED */
+    int32_t variant;      /* stencil kernel variant (tile shape); -1 = library default */
+    int32_t smax;         /* largest stage count accepted (coefficient table size); 0 = 1024
+                             for one grid, 64 for several (a batched super-step issues
+                             one stage launch per stage up to smax) */
+    int32_t reserved;
+} rkl_options;
+
+/*
+ * rkl_plan: validate `ngrids` grid descriptors and allocate the plan's device
+ * scratch (two FP64 stage buffers, the tau*M(Y0) buffer, reduction space and
+ * the RKL2 coefficient table for s = 2..smax, Appendix A).  Grids are packed
+ * back to back for the batched entry points; rkl_grid_offset gives each
+ * grid's first cell.  The device current at this call is the plan's device.
+ * Errors: RKL_EINVAL for a bad descriptor, RKL_ENOMEM, RKL_EDEVICE.
+ */
+rkl_status rkl_plan(const rkl_grid_desc *grids, int32_t ngrids, const rkl_options *opt,
+                    rkl_plan_t *plan_out);
+
+/* rkl_destroy: free the plan and its graph (NULL is accepted).  Synchronises
+ * the device. */
+rkl_status rkl_destroy(rkl_plan_t plan);
+
+/* Cells in the packed layout before grid `grid` (b of that grid starts at
+ * 3 * offset).  Returns -1 for a bad plan or index. */
+int64_t rkl_grid_offset(rkl_plan_t plan, int32_t grid);
+
+/*
+ * rkl_flux_div: out[i] = (gamma-1)/rho * ( -div F_c(T) )_i for one grid
+ * (Sec. 3: the face-difference divergence of the flux of Eqs. Fc-Fsat), in
+ * the plan's flux precision, written as double.  T, b, out: device pointers
+ * of that grid's size; out must not alias T.  No host synchronisation.
+ */
+rkl_status rkl_flux_div(rkl_plan_t plan, int32_t grid, const double *T, const void *b,
+                        double *out, void *stream);
+
+/*
+ * rkl_dt_par: the explicit parabolic step of Eq. dt_exp with the HD
+ * diffusivity, dt_par = cp / max_i[(gamma-1)/rho * kappa_par(T_i) * sum_d h_d^-2]
+ * (+inf when the maximum is 0).  Writes the host double *dt_par_out and
+ * synchronises `stream`.
+ */
+rkl_status rkl_dt_par(rkl_plan_t plan, int32_t grid, const double *T, double *dt_par_out,
+                      void *stream);
+
+/*
+ * rkl_superstep: one RKL2 super-step of length dt_hyp on one grid, T updated
+ * in place (Appendix A, Eq. rkl2scheme: Y0 = T, Y1 = Y0 + mut_1 tau M(Y0),
+ * Y_j = mu_j Y_{j-1} + nu_j Y_{j-2} + (1-mu_j-nu_j) Y0 + mut_j tau M(Y_{j-1})
+ * + gt_j tau M(Y0), T = Y_s), where M is the flux-divergence operator above
+ * evaluated on each stage's own temperature.  s = 1 + floor(root of
+ * dt_hyp/dt_par = (s^2+s-2)/4) is computed on the device (Eq. RKL-s); this
+ * entry point reads it back once (one synchronisation of `stream`) to size
+ * the launch sequence, and stores it in *s_out (host pointer, may be NULL).
+ * RKL_ESTAGES (T unchanged) if s > smax.  b must not alias T.
+ */
+rkl_status rkl_superstep(rkl_plan_t plan, int32_t grid, double *T, const void *b,
+                         double dt_hyp, int32_t *s_out, void *stream);
+
+/*
+ * rkl_superstep_batched: one super-step of every grid of the plan at once, in
+ * one persistent launch (plus a small reset kernel), with no host
+ * synchronisation -- safe to capture in a HIP graph.  T and b are packed
+ * (grid g at rkl_grid_offset(g) cells, b at 3x that); dt_hyp is a device
+ * array of ngrids doubles; s_out (device, ngrids int32, may be NULL) receives
+ * each grid's stage count.  A grid whose s exceeds smax is left unchanged
+ * and flagged (RKL_FLAG_STAGES, see rkl_query).
+ */
+rkl_status rkl_superstep_batched(rkl_plan_t plan, double *T, const void *b,
+                                 const double *dt_hyp, int32_t *s_out, void *stream);
+
+/*
+ * rkl_graph_capture: record rkl_superstep_batched(plan, T, b, dt_hyp, s_out)
+ * into a HIP graph owned by the plan (replacing any earlier one); nothing is
+ * executed.  rkl_graph_launch replays it on `stream` (one launch per
+ * super-step).  The pointers captured must stay valid while the graph is used.
+ */
+rkl_status rkl_graph_capture(rkl_plan_t plan, double *T, const void *b, const double *dt_hyp,
+                             int32_t *s_out, void *stream);
+rkl_status rkl_graph_launch(rkl_plan_t plan, void *stream);
+
+/*
+ * rkl_query: the last stage count, dt_par and flag bits (RKL_FLAG_*) computed
+ * for `grid` by the last super-step, flux_div or dt_par call.  Synchronises
+ * the plan's device.  Any output pointer may be NULL.
+ */
+rkl_status rkl_query(rkl_plan_t plan, int32_t grid, int32_t *last_s, double *last_dt_par,
+                     uint32_t *flags);
+
+/* Stencil kernel variants: rkl_variant_count() of them, each a tile shape
+ * (rkl_variant_info fills tile_x, tile_y, tile_z cells).  rkl_set_variant
+ * selects one for a plan (used by the autotuner). */
+int32_t rkl_variant_count(void);
+rkl_status rkl_variant_info(int32_t variant, int32_t *tile_x, int32_t *tile_y, int32_t *tile_z);
+rkl_status rkl_set_variant(rkl_plan_t plan, int32_t variant);
+
+/*
+ * Kernel timing for benchmarks.  rkl_profile(plan, 1) starts recording, with
+ * HIP events on the caller's stream, the span of the stage-j >= 2 stencil
+ * kernels of every following rkl_superstep (the s-1 back-to-back launches of
+ * the dominant kernel); rkl_profile(plan, 0) stops and discards.
+ * rkl_profile_read synchronises, and returns the summed span in ms, the
+ * number of kernel launches and of cell-stage updates it covers.
+ */
+rkl_status rkl_profile(rkl_plan_t plan, int32_t enable);
+rkl_status rkl_profile_read(rkl_plan_t plan, double *ms, int64_t *launches, int64_t *cell_stages);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *rkl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RKL_H */

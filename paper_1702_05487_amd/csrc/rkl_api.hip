@@ -1,0 +1,435 @@
+// rkl_api.hip -- host side of librkl's C ABI (include/rkl.h): descriptor
+// validation, plan scratch, the RKL2 coefficient table, and the launch
+// sequences of the single-grid entry points.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rkl.h"
+#include "rkl_internal.h"
+#include "rkl_batch.h"
+
+using namespace rkl;
+
+static thread_local std::string g_err;
+
+static rkl_status fail(rkl_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+static rkl_status hipfail(hipError_t e, const char* what) {
+    return fail(RKL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHECK(call, what)                   \
+    do {                                       \
+        hipError_t e_ = (call);                \
+        if (e_ != hipSuccess) return hipfail(e_, what); \
+    } while (0)
+
+struct rkl_plan_s {
+    int device = 0;
+    int ngrids = 0;
+    int precision = RKL_FP64;
+    int variant = 0;
+    int smax = 1024;
+    std::vector<rkl_grid_desc> desc;
+    std::vector<GridConst> gc;
+    std::vector<int64_t> off;   // packed cell offsets, ngrids + 1 entries
+    int64_t total = 0;
+    double* Ya = nullptr;       // stage buffers (FP64), packed
+    double* Yb = nullptr;
+    void* MY0 = nullptr;        // tau M(Y0), FP64 or FP32, packed
+    double* coef = nullptr;     // RKL2 table, device
+    GridState* state = nullptr; // ngrids entries, device
+    double* partials = nullptr; // 3 x 1024 doubles
+    int32_t* s_dev = nullptr;   // scratch for the stage-count read-back
+    int32_t* s_host = nullptr;  // pinned
+    BatchPlan* batch = nullptr; // batched launch data (rkl_batch.hip)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    // kernel timing (rkl_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;   // start/stop pairs
+    int64_t prof_launches = 0, prof_cells = 0;
+};
+
+static void prof_clear(rkl_plan_s* p) {
+    for (hipEvent_t e : p->ev) hipEventDestroy(e);
+    p->ev.clear();
+    p->prof_launches = p->prof_cells = 0;
+}
+
+// ---------------------------------------------------------------------------
+// RKL2 coefficients (Appendix A): for s stages, w1 = 4/(s^2+s-2),
+// b_j = (j^2+j-2)/(2j(j+1)) (b_0 = b_1 = b_2 = 1/3), a_j = 1 - b_j,
+// mut_1 = b_1 w1, mu_j = (2j-1)/j b_j/b_{j-1}, nu_j = -(j-1)/j b_j/b_{j-2},
+// mut_j = mu_j w1, gt_j = -a_{j-1} mut_j.  Row j of s holds
+// {mu_j, nu_j, 1 - mu_j - nu_j, mut_j, gt_j} at 5 (s(s+1)/2 + j).
+static std::vector<double> coefficient_table(int smax) {
+    const size_t rows = (size_t)(smax + 1) * (smax + 2) / 2;
+    std::vector<double> t(rows * 5, 0.0);
+    std::vector<double> bj(smax + 1);
+    for (int j = 0; j <= smax; ++j)
+        bj[j] = j <= 2 ? 1.0 / 3.0 : ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
+    for (int s = 2; s <= smax; ++s) {
+        const double w1 = 4.0 / ((double)s * s + s - 2.0);
+        double* row = &t[5 * ((size_t)s * (s + 1) / 2)];
+        row[5 * 1 + 3] = bj[1] * w1;
+        for (int j = 2; j <= s; ++j) {
+            const double mu = (2.0 * j - 1.0) / j * bj[j] / bj[j - 1];
+            const double nu = -(j - 1.0) / j * bj[j] / bj[j - 2];
+            const double mut = mu * w1;
+            double* r = row + 5 * j;
+            r[0] = mu;
+            r[1] = nu;
+            r[2] = 1.0 - mu - nu;
+            r[3] = mut;
+            r[4] = -(1.0 - bj[j - 1]) * mut;
+        }
+    }
+    return t;
+}
+
+static bool validate(const rkl_grid_desc& g, std::string& why) {
+    char buf[160];
+    if (g.ndim < 1 || g.ndim > 3) { why = "ndim must be 1, 2 or 3"; return false; }
+    for (int d = 0; d < 3; ++d) {
+        if (g.n[d] < 1) { snprintf(buf, sizeof buf, "n[%d] = %d must be >= 1", d, g.n[d]); why = buf; return false; }
+        if (d >= g.ndim && g.n[d] != 1) { snprintf(buf, sizeof buf, "n[%d] must be 1 when ndim = %d", d, g.ndim); why = buf; return false; }
+        if (!(g.h[d] > 0.0) || !std::isfinite(g.h[d])) { snprintf(buf, sizeof buf, "h[%d] must be finite and > 0", d); why = buf; return false; }
+    }
+    if ((int64_t)g.n[0] * g.n[1] > (int64_t)1 << 30 ||
+        (int64_t)g.n[0] * g.n[1] * g.n[2] > ((int64_t)1 << 32)) { why = "grid too large"; return false; }
+    if (g.limiter != RKL_LIM_NONE && g.limiter != RKL_LIM_MC) { why = "limiter must be RKL_LIM_NONE or RKL_LIM_MC"; return false; }
+    if (g.saturation != 0 && g.saturation != 1) { why = "saturation must be 0 or 1"; return false; }
+    if (g.saturation && !(g.phi > 0.0 && std::isfinite(g.phi))) { why = "phi must be > 0"; return false; }
+    if (!(g.kappa0 >= 0.0) || !std::isfinite(g.kappa0)) { why = "kappa0 must be finite and >= 0"; return false; }
+    if (!(g.kappa_exp >= 0.0) || !std::isfinite(g.kappa_exp)) { why = "kappa_exp must be finite and >= 0"; return false; }
+    if (!(g.kperp_ratio >= 0.0 && g.kperp_ratio <= 1.0)) { why = "kperp_ratio must be in [0, 1]"; return false; }
+    if (!(g.rho > 0.0) || !std::isfinite(g.rho)) { why = "rho must be finite and > 0"; return false; }
+    if (!(g.gamma > 1.0) || !std::isfinite(g.gamma)) { why = "gamma must be finite and > 1"; return false; }
+    if (!(g.cp > 0.0 && g.cp <= 0.5)) { why = "cp must be in (0, 1/2]"; return false; }
+    return true;
+}
+
+static GridConst make_const(const rkl_grid_desc& g) {
+    GridConst c;
+    c.n0 = g.n[0];
+    c.n1 = g.n[1];
+    c.n2 = g.n[2];
+    c.ndim = g.ndim;
+    c.ih0 = 1.0 / g.h[0];
+    c.ih1 = 1.0 / g.h[1];
+    c.ih2 = 1.0 / g.h[2];
+    c.kappa0 = g.kappa0;
+    c.kexp = g.kappa_exp;
+    c.kperp = g.kperp_ratio;
+    c.satq = 5.0 * g.phi * g.rho;
+    c.kmode = g.kappa_exp == 0.0 ? 0 : (g.kappa_exp == 2.5 ? 1 : 2);
+    c.limiter = g.limiter;
+    c.saturation = g.saturation;
+    c.fac = (g.gamma - 1.0) / g.rho;
+    c.cp = g.cp;
+    double s = 0.0;
+    for (int d = 0; d < g.ndim; ++d) s += 1.0 / (g.h[d] * g.h[d]);
+    c.ihsum = s;
+    return c;
+}
+
+static void free_plan(rkl_plan_s* p) {
+    if (!p) return;
+    prof_clear(p);
+    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    batch_free(p->batch);
+    hipFree(p->Ya);
+    hipFree(p->Yb);
+    hipFree(p->MY0);
+    hipFree(p->coef);
+    hipFree(p->state);
+    hipFree(p->partials);
+    hipFree(p->s_dev);
+    if (p->s_host) hipHostFree(p->s_host);
+    delete p;
+}
+
+extern "C" {
+
+const char* rkl_last_error(void) { return g_err.c_str(); }
+
+int32_t rkl_variant_count(void) { return variant_count(); }
+
+rkl_status rkl_variant_info(int32_t v, int32_t* tx, int32_t* ty, int32_t* tz) {
+    if (v < 0 || v >= variant_count()) return fail(RKL_EINVAL, "variant out of range");
+    const Variant x = variant_get(v);
+    if (tx) *tx = x.bx;
+    if (ty) *ty = x.by;
+    if (tz) *tz = x.bz;
+    return RKL_OK;
+}
+
+rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_options* opt, rkl_plan_t* out) {
+    if (!out) return fail(RKL_EINVAL, "plan_out is NULL");
+    *out = nullptr;
+    if (!grids || ngrids < 1) return fail(RKL_EINVAL, "need at least one grid descriptor");
+    rkl_options o = {RKL_FP64, -1, 0, 0};
+    if (opt) o = *opt;
+    if (o.precision != RKL_FP64 && o.precision != RKL_MIXED) return fail(RKL_EINVAL, "precision must be RKL_FP64 or RKL_MIXED");
+    if (o.smax == 0) o.smax = ngrids > 1 ? 64 : 1024;
+    if (o.smax < 2 || o.smax > 4096) return fail(RKL_EINVAL, "smax must be in [2, 4096]");
+    if (o.variant < -1 || o.variant >= variant_count()) return fail(RKL_EINVAL, "variant out of range");
+
+    rkl_plan_s* p = new rkl_plan_s();
+    p->ngrids = ngrids;
+    p->precision = o.precision;
+    p->variant = o.variant < 0 ? 0 : o.variant;
+    p->smax = o.smax;
+    p->off.push_back(0);
+    for (int g = 0; g < ngrids; ++g) {
+        std::string why;
+        if (!validate(grids[g], why)) {
+            delete p;
+            return fail(RKL_EINVAL, "grid " + std::to_string(g) + ": " + why);
+        }
+        p->desc.push_back(grids[g]);
+        p->gc.push_back(make_const(grids[g]));
+        const int64_t n = (int64_t)grids[g].n[0] * grids[g].n[1] * grids[g].n[2];
+        p->off.push_back(p->off.back() + n);
+    }
+    p->total = p->off.back();
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { free_plan(p); return hipfail(e, "hipGetDevice"); }
+
+    const size_t rs = o.precision == RKL_MIXED ? sizeof(float) : sizeof(double);
+    const std::vector<double> tab = coefficient_table(o.smax);
+    bool ok = hipMalloc(&p->Ya, sizeof(double) * p->total) == hipSuccess &&
+              hipMalloc(&p->Yb, sizeof(double) * p->total) == hipSuccess &&
+              hipMalloc(&p->MY0, rs * p->total) == hipSuccess &&
+              hipMalloc(&p->coef, sizeof(double) * tab.size()) == hipSuccess &&
+              hipMalloc(&p->state, sizeof(GridState) * ngrids) == hipSuccess &&
+              hipMalloc(&p->partials, sizeof(double) * 3 * 1024) == hipSuccess &&
+              hipMalloc(&p->s_dev, sizeof(int32_t)) == hipSuccess &&
+              hipHostMalloc((void**)&p->s_host, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        free_plan(p);
+        return fail(RKL_ENOMEM, "device allocation failed");
+    }
+    e = hipMemcpy(p->coef, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->state, 0, sizeof(GridState) * ngrids);
+    if (e != hipSuccess) { free_plan(p); return hipfail(e, "plan upload"); }
+    if (ngrids > 1) {
+        std::string why;
+        rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, &p->batch, why);
+        if (st != RKL_OK) { free_plan(p); return fail(st, why); }
+    }
+    *out = p;
+    return RKL_OK;
+}
+
+rkl_status rkl_destroy(rkl_plan_t p) {
+    if (!p) return RKL_OK;
+    hipDeviceSynchronize();
+    free_plan(p);
+    return RKL_OK;
+}
+
+int64_t rkl_grid_offset(rkl_plan_t p, int32_t g) {
+    if (!p || g < 0 || g > p->ngrids) return -1;
+    return p->off[g];
+}
+
+rkl_status rkl_set_variant(rkl_plan_t p, int32_t v) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (v < 0 || v >= variant_count()) return fail(RKL_EINVAL, "variant out of range");
+    p->variant = v;
+    return RKL_OK;
+}
+
+static rkl_status check_grid(rkl_plan_t p, int32_t g) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (g < 0 || g >= p->ngrids) return fail(RKL_EINVAL, "grid index out of range");
+    return RKL_OK;
+}
+
+// min/max reduction of T and the finalize step for grid g
+static rkl_status reduce_and_finalize(rkl_plan_t p, int32_t g, const double* T, double dt_hyp, int mode,
+                                      int32_t* s_dev, hipStream_t st) {
+    const int64_t N = p->off[g + 1] - p->off[g];
+    const int nb = reduce_blocks(N);
+    HIPCHECK(launch_reduce(T, N, p->partials, nb, st), "reduce launch");
+    HIPCHECK(launch_finalize(p->partials, nb, p->gc[g], dt_hyp, mode, p->state + g, s_dev, p->smax, st),
+             "finalize launch");
+    return RKL_OK;
+}
+
+rkl_status rkl_flux_div(rkl_plan_t p, int32_t g, const double* T, const void* b, double* out, void* stream) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    if (!T || !b || !out) return fail(RKL_EINVAL, "NULL field pointer");
+    if (out == T) return fail(RKL_EINVAL, "out must not alias T");
+    hipStream_t s = (hipStream_t)stream;
+    st = reduce_and_finalize(p, g, T, 0.0, 1, nullptr, s);
+    if (st != RKL_OK) return st;
+    HIPCHECK(launch_stage(p->precision, p->variant, p->gc[g], 0, 0, T, nullptr, nullptr, nullptr, nullptr,
+                          out, b, p->state + g, p->coef, s),
+             "flux_div launch");
+    return RKL_OK;
+}
+
+rkl_status rkl_dt_par(rkl_plan_t p, int32_t g, const double* T, double* dt_par_out, void* stream) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    if (!T || !dt_par_out) return fail(RKL_EINVAL, "NULL pointer");
+    hipStream_t s = (hipStream_t)stream;
+    st = reduce_and_finalize(p, g, T, 0.0, 1, nullptr, s);
+    if (st != RKL_OK) return st;
+    double v = 0.0;
+    HIPCHECK(hipMemcpyAsync(&v, &p->state[g].dt_par, sizeof(double), hipMemcpyDeviceToHost, s), "dt_par copy");
+    HIPCHECK(hipStreamSynchronize(s), "dt_par sync");
+    *dt_par_out = v;
+    return RKL_OK;
+}
+
+rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, double dt_hyp, int32_t* s_out,
+                         void* stream) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    st = reduce_and_finalize(p, g, T, dt_hyp, 0, p->s_dev, s);
+    if (st != RKL_OK) return st;
+    HIPCHECK(hipMemcpyAsync(p->s_host, p->s_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s), "s copy");
+    HIPCHECK(hipStreamSynchronize(s), "s sync");
+    const int S = *p->s_host;
+    if (s_out) *s_out = S;
+    if (S < 2 || S > p->smax)
+        return fail(RKL_ESTAGES, "stage count " + std::to_string(S) + " outside [2, smax=" + std::to_string(p->smax) + "]");
+
+    const GridConst& gc = p->gc[g];
+    double* A = p->Ya + p->off[g];
+    double* B = p->Yb + p->off[g];
+    const size_t rs = p->precision == RKL_MIXED ? sizeof(float) : sizeof(double);
+    void* M = (char*)p->MY0 + rs * p->off[g];
+    const GridState* gs = p->state + g;
+    // stage 1: Y1 = Y0 + mut_1 tau M(Y0), tau M(Y0) kept for the later stages
+    HIPCHECK(launch_stage(p->precision, p->variant, gc, 1, 1, T, nullptr, nullptr, nullptr, M, A, b, gs, p->coef, s),
+             "stage 1 launch");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (p->prof) {
+        HIPCHECK(hipEventCreate(&e0), "event create");
+        HIPCHECK(hipEventCreate(&e1), "event create");
+        p->ev.push_back(e0);
+        p->ev.push_back(e1);
+        HIPCHECK(hipEventRecord(e0, s), "event record");
+    }
+    const double* ym1 = A;
+    const double* ym2 = T;
+    for (int j = 2; j <= S; ++j) {
+        double* out = j == S ? T : (j == 2 ? B : const_cast<double*>(ym2));
+        HIPCHECK(launch_stage(p->precision, p->variant, gc, 2, j, ym1, ym2, T, M, nullptr, out, b, gs, p->coef, s),
+                 "stage launch");
+        ym2 = ym1;
+        ym1 = out;
+    }
+    if (p->prof) {
+        HIPCHECK(hipEventRecord(e1, s), "event record");
+        p->prof_launches += S - 1;
+        p->prof_cells += (int64_t)(S - 1) * (p->off[g + 1] - p->off[g]);
+    }
+    return RKL_OK;
+}
+
+rkl_status rkl_profile(rkl_plan_t p, int32_t enable) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    HIPCHECK(hipDeviceSynchronize(), "profile sync");
+    prof_clear(p);
+    p->prof = enable != 0;
+    return RKL_OK;
+}
+
+rkl_status rkl_profile_read(rkl_plan_t p, double* ms, int64_t* launches, int64_t* cells) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < p->ev.size(); i += 2) {
+        HIPCHECK(hipEventSynchronize(p->ev[i + 1]), "event sync");
+        float t = 0.f;
+        HIPCHECK(hipEventElapsedTime(&t, p->ev[i], p->ev[i + 1]), "event elapsed");
+        tot += t;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = p->prof_launches;
+    if (cells) *cells = p->prof_cells;
+    return RKL_OK;
+}
+
+rkl_status rkl_query(rkl_plan_t p, int32_t g, int32_t* last_s, double* last_dt_par, uint32_t* flags) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    GridState h;
+    HIPCHECK(hipDeviceSynchronize(), "query sync");
+    HIPCHECK(hipMemcpy(&h, p->state + g, sizeof h, hipMemcpyDeviceToHost), "query copy");
+    if (last_s) *last_s = h.s;
+    if (last_dt_par) *last_dt_par = h.dt_par;
+    if (flags) *flags = h.flags;
+    return RKL_OK;
+}
+
+rkl_status rkl_superstep_batched(rkl_plan_t p, double* T, const void* b, const double* dt_hyp, int32_t* s_out,
+                                 void* stream) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
+    if (!p->batch) {
+        std::string why;
+        rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, &p->batch, why);
+        if (st != RKL_OK) return fail(st, why);
+    }
+    BatchBuffers bb{T, b, dt_hyp, s_out, p->Ya, p->Yb, p->MY0, p->coef, p->state};
+    hipError_t e = batch_launch(p->batch, bb, (hipStream_t)stream);
+    if (e != hipSuccess) return hipfail(e, "batched launch");
+    return RKL_OK;
+}
+
+rkl_status rkl_graph_capture(rkl_plan_t p, double* T, const void* b, const double* dt_hyp, int32_t* s_out,
+                             void* stream) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
+    if (!p->batch) {
+        std::string why;
+        rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, &p->batch, why);
+        if (st != RKL_OK) return fail(st, why);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipStream_t cap;
+    HIPCHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { hipStreamDestroy(cap); return hipfail(e, "begin capture"); }
+    BatchBuffers bb{T, b, dt_hyp, s_out, p->Ya, p->Yb, p->MY0, p->coef, p->state};
+    hipError_t le = batch_launch(p->batch, bb, cap);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(cap, &gr);
+    hipStreamDestroy(cap);
+    if (le != hipSuccess) { if (gr) hipGraphDestroy(gr); return hipfail(le, "batched launch under capture"); }
+    if (e != hipSuccess) return hipfail(e, "end capture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) { hipGraphDestroy(gr); return hipfail(e, "graph instantiate"); }
+    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->graph = gr;
+    p->graph_exec = ex;
+    (void)s;
+    return RKL_OK;
+}
+
+rkl_status rkl_graph_launch(rkl_plan_t p, void* stream) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (!p->graph_exec) return fail(RKL_ESTATE, "no graph captured");
+    HIPCHECK(hipGraphLaunch(p->graph_exec, (hipStream_t)stream), "graph launch");
+    return RKL_OK;
+}
+
+}  // extern "C"

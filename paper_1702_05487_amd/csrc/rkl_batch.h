@@ -1,0 +1,32 @@
+// rkl_batch.h -- the batched (many-grid) super-step of librkl.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/rkl.h"
+#include "rkl_internal.h"
+
+namespace rkl {
+
+struct BatchPlan;
+
+struct BatchBuffers {
+    double* T;             // packed temperatures (updated in place)
+    const void* b;         // packed unit vectors, 3 x cells per grid
+    const double* dt_hyp;  // device, ngrids
+    int32_t* s_out;        // device, ngrids, may be NULL
+    double* Ya;            // packed stage buffers (plan scratch)
+    double* Yb;
+    void* MY0;
+    const double* coef;    // RKL2 table
+    GridState* state;      // ngrids
+};
+
+rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vector<GridConst>& gc,
+                        const std::vector<int64_t>& off, int precision, int smax, BatchPlan** out,
+                        std::string& why);
+void batch_free(BatchPlan* bp);
+// Enqueue one super-step of every grid (no host synchronisation).
+hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st);
+
+}  // namespace rkl

@@ -1,0 +1,92 @@
+// rkl_internal.h -- declarations shared by librkl's own translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rkl {
+
+// Device-resident per-grid state, written by the finalize step of every
+// super-step / flux_div / dt_par call and read by the stage kernels.
+struct GridState {
+    double dt_par;   // explicit parabolic step (Eq. dt_exp), +inf if no conduction
+    double tau;      // super-step length
+    double cdiv;     // tau * (gamma-1)/rho
+    double tref;     // reference temperature subtracted before FP32 flux arithmetic
+    double tmax, tmin;
+    int32_t s;       // RKL2 stage count (0 when not a super-step)
+    uint32_t flags;  // RKL_FLAG_* bits
+};
+
+// Per-grid constants (host-computed in FP64 from the descriptor).
+struct GridConst {
+    int n0, n1, n2, ndim;
+    double ih0, ih1, ih2;   // 1/h
+    double kappa0, kexp, kperp, satq;  // satq = 5 phi rho
+    int kmode;              // 0: kappa0, 1: kappa0 T^2.5, 2: kappa0 T^kexp
+    int limiter, saturation;
+    double fac;             // (gamma-1)/rho
+    double cp, ihsum;       // Courant number, sum_d 1/h_d^2 over active axes
+};
+
+// kappa_par at a temperature, FP64, with the operation order of the scalar
+// definition kappa0 * (T*T*sqrt(T)) so that dt_par is reproducible
+__device__ inline double kappa_at(const GridConst& g, double T) {
+    const double t = T > 0.0 ? T : 0.0;
+    if (g.kmode == 0) return g.kappa0;
+    if (g.kmode == 1) return g.kappa0 * (t * t * sqrt(t));
+    return g.kappa0 * pow(t, g.kexp);
+}
+
+// Turn the temperature maximum/minimum of a grid into its state: dt_par of
+// Eq. dt_exp with chi = kappa_par (gamma-1)/rho (kappa_par is non-decreasing
+// in T, so its maximum over cells is kappa_par(max T)) and, for a super-step
+// (mode 0), the stage count of Eq. RKL-s, dt_hyp = dt_par (s^2+s-2)/4, with
+// its root rounded up as 1 + floor(s).  flag bits as in rkl.h.
+__device__ inline GridState finalize_state(const GridConst& g, double mx, double mn, bool bad,
+                                           double dt_hyp, int mode, int smax) {
+#pragma clang fp contract(off)
+    uint32_t flags = 0;
+    if (bad) flags |= 2u;          // RKL_FLAG_NONFINITE
+    if (mn <= 0.0) flags |= 1u;    // RKL_FLAG_NONPOS
+    const double lam = g.fac * kappa_at(g, mx) * g.ihsum;
+    const double dtp = lam > 0.0 ? g.cp / lam : INFINITY;
+    int32_t s = 0;
+    if (mode == 0) {
+        const double r = isinf(dtp) ? 0.0 : dt_hyp / dtp;
+        const double sr = (-1.0 + sqrt(9.0 + 16.0 * r)) / 2.0;
+        const double sf = floor(sr);
+        s = (sf >= 0.0 && sf < 1e9) ? 1 + (int32_t)sf : 0x7fffffff;
+        if (s > smax) flags |= 4u; // RKL_FLAG_STAGES
+    }
+    GridState o;
+    o.dt_par = dtp;
+    o.tau = dt_hyp;
+    o.cdiv = dt_hyp * g.fac;
+    o.tref = 0.5 * (mx + mn);
+    if (!isfinite(o.tref)) o.tref = 0.0;
+    o.tmax = mx;
+    o.tmin = mn;
+    o.s = s;
+    o.flags = flags;
+    return o;
+}
+
+// Kernel variants of the single-grid stencil: tile shape and z-chunk length.
+struct Variant {
+    int bx, by, bz;
+};
+int variant_count();
+Variant variant_get(int v);
+
+// Launchers (enqueue only; return the HIP error of the launch).
+hipError_t launch_reduce(const double* T, int64_t N, double* partials, int nblocks, hipStream_t st);
+int reduce_blocks(int64_t N);
+hipError_t launch_finalize(const double* partials, int nblocks, const GridConst& gc, double dt_hyp,
+                           int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st);
+// kind: 0 flux divergence into Yout, 1 first stage, 2 stage j >= 2
+hipError_t launch_stage(int precision, int variant, const GridConst& gc, int kind, int stage,
+                        const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
+                        void* MY0out, double* Yout, const void* b, const GridState* state,
+                        const double* coef, hipStream_t st);
+
+}  // namespace rkl

@@ -1,0 +1,221 @@
+// rkl_kernels.hip -- single-grid kernels of librkl for gfx950: the
+// temperature min/max reduction, the finalize step that turns it into
+// dt_par, the stage count s and the stage scale (Sec. 3.1 Eq. dt_exp,
+// Sec. 3.3 Eq. RKL-s, Sec. 4.1 rounding), and the stencil/stage kernels that
+// wrap run_tile (rkl_tile.h).
+#include "rkl_internal.h"
+#include "rkl_tile.h"
+#include "../../include/rkl.h"
+
+namespace rkl {
+
+// ------------------------------------------------------------ variants ----
+// (bx, by) are compile-time tile shapes; bz is the z-chunk length per block.
+static const Variant kVariants[] = {
+    {32, 8, 32}, {32, 8, 64}, {64, 4, 32}, {64, 4, 64}, {16, 16, 32}, {16, 16, 64},
+    {32, 8, 16}, {64, 4, 16},
+};
+int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+Variant variant_get(int v) { return kVariants[v]; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that
+// consecutive logical tiles (which share halo lines) land on the same XCD and
+// its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb / 8, r = nb % 8;
+    const int xcd = b % 8, slot = b / 8;
+    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+// ----------------------------------------------------------- reduction ----
+// per-block maximum, minimum and a non-finite flag of T
+__global__ __launch_bounds__(256) void reduce_minmax_kernel(const double* __restrict__ T, int64_t N,
+                                                            double* __restrict__ part) {
+    double mx = -INFINITY, mn = INFINITY, bad = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+        const double v = T[i];
+        mx = fmax(mx, v);
+        mn = fmin(mn, v);
+        bad = isfinite(v) ? bad : 1.0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, off));
+        mn = fmin(mn, __shfl_xor(mn, off));
+        bad = fmax(bad, __shfl_xor(bad, off));
+    }
+    __shared__ double sm[3][4];
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    if (l == 0) { sm[0][w] = mx; sm[1][w] = mn; sm[2][w] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 4; ++i) {
+            mx = fmax(mx, sm[0][i]);
+            mn = fmin(mn, sm[1][i]);
+            bad = fmax(bad, sm[2][i]);
+        }
+        part[3 * blockIdx.x + 0] = mx;
+        part[3 * blockIdx.x + 1] = mn;
+        part[3 * blockIdx.x + 2] = bad;
+    }
+}
+
+int reduce_blocks(int64_t N) {
+    int64_t b = (N + 255) / 256;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+hipError_t launch_reduce(const double* T, int64_t N, double* partials, int nblocks, hipStream_t st) {
+    reduce_minmax_kernel<<<nblocks, 256, 0, st>>>(T, N, partials);
+    return hipGetLastError();
+}
+
+// mode 0: super-step (computes s); mode 1: flux_div / dt_par only (s = 0)
+__global__ __launch_bounds__(64) void finalize_kernel(const double* __restrict__ part, int nb, GridConst g,
+                                                      double dt_hyp, int mode, GridState* st,
+                                                      int32_t* s_out, int smax) {
+    double mx = -INFINITY, mn = INFINITY, bad = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 64) {
+        mx = fmax(mx, part[3 * i]);
+        mn = fmin(mn, part[3 * i + 1]);
+        bad = fmax(bad, part[3 * i + 2]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, off));
+        mn = fmin(mn, __shfl_xor(mn, off));
+        bad = fmax(bad, __shfl_xor(bad, off));
+    }
+    if (threadIdx.x != 0) return;
+    const GridState o = finalize_state(g, mx, mn, bad != 0.0, dt_hyp, mode, smax);
+    *st = o;
+    if (s_out) *s_out = o.s;
+}
+
+hipError_t launch_finalize(const double* partials, int nblocks, const GridConst& gc, double dt_hyp,
+                           int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st) {
+    finalize_kernel<<<1, 64, 0, st>>>(partials, nblocks, gc, dt_hyp, mode, state, s_out, smax);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------- stage kernels ----
+struct StageLaunch {
+    TileArgs t;          // everything but the tile origin, z range and coefficients
+    int ntx, nty, bz;
+    const GridState* state;
+    const double* coef;  // RKL2 table: 5 doubles per (s, j), row of s at s(s+1)/2
+    int stage;
+    double kappa0, kexp, kperp, satq;
+    int kmode;
+    double fac;
+};
+
+template <typename R, bool LIM, bool SAT, int BX, int BY>
+__global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
+    constexpr int PL = (BX + 2) * (BY + 2);
+    __shared__ TileLds<R, PL, (BX + 1) * BY, BX*(BY + 1)> L;
+    int bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile_x = bid % P.ntx;
+    bid /= P.ntx;
+    const int tile_y = bid % P.nty;
+    const int zc = bid / P.nty;
+
+    TileArgs a = P.t;
+    a.bx = BX;
+    a.by = BY;
+    a.x0 = tile_x * BX;
+    a.y0 = tile_y * BY;
+    a.z0 = zc * P.bz;
+    a.z1 = min(a.z0 + P.bz, a.n2);
+
+    const GridState* st = P.state;
+    double tref = 0.0;
+    if (sizeof(R) == 4) tref = st->tref;
+    if (a.kind == 0) {
+        a.scale = -P.fac;
+    } else {
+        const int s = st->s;
+        const double* cf = P.coef + 5 * ((size_t)s * (s + 1) / 2 + P.stage);
+        a.mu = cf[0];
+        a.nu = cf[1];
+        a.omn = cf[2];
+        a.mut = cf[3];
+        a.gt = cf[4];
+        a.scale = -st->cdiv;
+    }
+    FaceK<R> fk;
+    fk.kappa0 = R(P.kappa0);
+    fk.kexp = R(P.kexp);
+    fk.kperp = R(P.kperp);
+    fk.satq = R(P.satq);
+    fk.tref = R(tref);
+    fk.kmode = P.kmode;
+    run_tile<R, LIM, SAT>(a, fk, tref, L);
+}
+
+template <typename R, int BX, int BY>
+static hipError_t launch_shape(const StageLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
+    if (lim && sat) stage_kernel<R, true, true, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    else if (lim) stage_kernel<R, true, false, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    else if (sat) stage_kernel<R, false, true, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    else stage_kernel<R, false, false, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_prec(const StageLaunch& P, int nblocks, int bx, int by, bool lim, bool sat,
+                              hipStream_t st) {
+    if (bx == 32 && by == 8) return launch_shape<R, 32, 8>(P, nblocks, lim, sat, st);
+    if (bx == 64 && by == 4) return launch_shape<R, 64, 4>(P, nblocks, lim, sat, st);
+    if (bx == 16 && by == 16) return launch_shape<R, 16, 16>(P, nblocks, lim, sat, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage(int precision, int variant, const GridConst& gc, int kind, int stage,
+                        const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
+                        void* MY0out, double* Yout, const void* b, const GridState* state,
+                        const double* coef, hipStream_t st) {
+    const Variant v = variant_get(variant);
+    StageLaunch P;
+    TileArgs& a = P.t;
+    a.Yin = Yin;
+    a.Ym2 = Ym2;
+    a.Y0 = Y0;
+    a.MY0in = MY0in;
+    a.MY0out = MY0out;
+    a.Yout = Yout;
+    a.b = b;
+    a.n0 = gc.n0;
+    a.n1 = gc.n1;
+    a.n2 = gc.n2;
+    a.ndim = gc.ndim;
+    a.x0 = a.y0 = a.z0 = a.z1 = 0;
+    a.bx = v.bx;
+    a.by = v.by;
+    a.kind = kind;
+    a.ih0 = gc.ih0;
+    a.ih1 = gc.ih1;
+    a.ih2 = gc.ih2;
+    a.scale = 0.0;
+    a.mu = a.nu = a.omn = a.mut = a.gt = 0.0;
+    P.ntx = (gc.n0 + v.bx - 1) / v.bx;
+    P.nty = (gc.n1 + v.by - 1) / v.by;
+    P.bz = v.bz;
+    const int nzc = (gc.n2 + v.bz - 1) / v.bz;
+    P.state = state;
+    P.coef = coef;
+    P.stage = stage;
+    P.kappa0 = gc.kappa0;
+    P.kexp = gc.kexp;
+    P.kperp = gc.kperp;
+    P.satq = gc.satq;
+    P.kmode = gc.kmode;
+    P.fac = gc.fac;
+    const int64_t nb = (int64_t)P.ntx * P.nty * nzc;
+    if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
+    const bool lim = gc.limiter != 0, sat = gc.saturation != 0;
+    if (precision == RKL_MIXED) return launch_prec<float>(P, (int)nb, v.bx, v.by, lim, sat, st);
+    return launch_prec<double>(P, (int)nb, v.bx, v.by, lim, sat, st);
+}
+
+}  // namespace rkl

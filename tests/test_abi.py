@@ -1,0 +1,80 @@
+"""The C-ABI library builds, loads and exports every entry point that
+include/rkl.h declares; descriptor validation answers without a GPU."""
+import os
+import re
+
+import pytest
+
+from paper_1702_05487_amd import rkl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "rkl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rkl_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = rkl.load()
+    names = header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(rkl.EXPORTS)
+
+
+def test_descriptor_struct_matches_header(tmp_path):
+    # the ctypes mirrors have the layout the C compiler gives the header's structs
+    import ctypes
+    import subprocess
+    fields = [f for f, _ in rkl.rkl_grid_desc._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "rkl.h"\nint main(void){\n'
+        'printf("%zu %zu\\n", sizeof(rkl_grid_desc), sizeof(rkl_options));\n'
+        + "".join('printf("%%zu\\n", offsetof(rkl_grid_desc, %s));\n' % f for f in fields)
+        + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    assert int(out[0]) == ctypes.sizeof(rkl.rkl_grid_desc)
+    assert int(out[1]) == ctypes.sizeof(rkl.rkl_options)
+    for f, off in zip(fields, out[2:]):
+        assert int(off) == getattr(rkl.rkl_grid_desc, f).offset, f
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ndim=4), dict(n=(0, 4, 4)), dict(n=(4, 4, 2), ndim=2), dict(h=(0.0, 1, 1)),
+    dict(limiter=2), dict(saturation=1, phi=0.0), dict(kappa0=-1.0), dict(kappa_exp=-0.5),
+    dict(kperp_ratio=1.5), dict(rho=0.0), dict(gamma=1.0), dict(cp=0.6), dict(cp=0.0),
+])
+def test_invalid_descriptors_are_rejected(bad):
+    base = dict(n=(8, 8, 8), h=(0.1, 0.1, 0.1), ndim=3)
+    base.update(bad)
+    d = rkl.grid_desc(**base)
+    with pytest.raises(rkl.RklError) as e:
+        rkl.rkl_plan([d])
+    assert e.value.status == rkl.RKL_EINVAL
+    assert rkl.rkl_last_error()
+
+
+def test_invalid_options_are_rejected():
+    d = rkl.grid_desc((8, 8, 8), (0.1,) * 3)
+    for kw in (dict(precision=7), dict(smax=1), dict(smax=5000), dict(variant=999)):
+        with pytest.raises(rkl.RklError) as e:
+            rkl.rkl_plan([d], **kw)
+        assert e.value.status == rkl.RKL_EINVAL
+    with pytest.raises(rkl.RklError):
+        rkl.rkl_plan([])
+
+
+def test_variant_table():
+    n = rkl.rkl_variant_count()
+    assert n >= 3
+    for v in range(n):
+        bx, by, bz = rkl.rkl_variant_info(v)
+        assert bx * by <= 1024 and bz >= 1
+    with pytest.raises(rkl.RklError):
+        rkl.rkl_variant_info(n)

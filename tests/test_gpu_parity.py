@@ -1,0 +1,233 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (rel-L1 = sum|gpu - oracle| / sum|oracle|):
+  FP64 plans: super-step rel-L1 <= 1e-12, flux divergence <= 1e-12 with
+  max |diff| <= 1e-11 max |ref|; identical stage counts.
+  Mixed plans (FP32 flux, FP64 stage recurrence): super-step rel-L1 <= 1e-5.
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import lib_desc, oracle_grid, rel_l1, sampled_superstep
+from paper_1702_05487_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1702_05487_amd import rkl
+    rkl.load(build_if_missing=False)
+    return torch
+
+
+def make_case(name):
+    """(n, h, ndim, params, T, b) for a named small case"""
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    if name == "gauss2d":
+        w = inputs.gaussian_pulse_2d(64)
+        return w.n, w.h, 2, dict(w.params), w.T, w.b
+    if name == "tangled_mc":
+        n = (48, 40, 36)
+        return n, tuple(1.0 / v for v in n), 3, dict(inputs.SPITZER_MC), \
+            inputs.noisy_temperature(n, 2, kmax=8), inputs.tangled_b(n, 1, kmax=8)
+    if name == "tangled_mc_sat":
+        n = (37, 23, 19)
+        p = dict(inputs.SPITZER_MC_SAT, phi=0.003)   # saturation active in a fraction of faces
+        return n, (0.03, 0.04, 0.05), 3, p, \
+            inputs.noisy_temperature(n, 4, kmax=4), inputs.tangled_b(n, 3, kmax=4)
+    if name == "iso1d":
+        n = (50, 1, 1)
+        T = 1.0 + 0.5 * rng.random((1, 1, 50))
+        b = np.zeros((3, 1, 1, 50))
+        b[0] = 1.0
+        return n, (0.02, 1.0, 1.0), 1, dict(inputs.BASE, kappa_exp=2.5), T, b
+    if name == "flat2d_ragged":
+        n = (45, 29, 1)
+        T = inputs.noisy_temperature(n, 6, kmax=6)
+        b = inputs.unit_vectors(rng.standard_normal((3, 1, 29, 45)))
+        return n, (0.02, 0.03, 1.0), 2, dict(inputs.SPITZER_MC_SAT, kperp_ratio=0.05), T, b
+    if name == "tiny3d":
+        n = (5, 3, 4)          # narrower than every tile: wrap inside one tile
+        T = 1.0 + 0.2 * rng.random((4, 3, 5))
+        b = inputs.unit_vectors(rng.standard_normal((3, 4, 3, 5)))
+        return n, (0.2, 0.3, 0.25), 3, dict(inputs.SPITZER_MC_SAT, phi=0.01), T, b
+    raise KeyError(name)
+
+
+CASES = ["gauss2d", "tangled_mc", "tangled_mc_sat", "iso1d", "flat2d_ragged", "tiny3d"]
+
+
+def to_dev(torch, a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda:0", dtype=dtype)
+
+
+def run_plan(torch, n, h, ndim, params, precision, variant=-1):
+    from paper_1702_05487_amd import rkl
+    return rkl.Plan([lib_desc(n, h, ndim, params)], precision=precision, variant=variant)
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("variant", [0, 2, 4])
+def test_flux_div_fp64(torch_cuda, name, variant):
+    torch = torch_cuda
+    n, h, ndim, p, T, b = make_case(name)
+    print("flux_div fp64", name, n, "variant", variant, flush=True)
+    ref = oracle.flux_div(oracle_grid(n, h, ndim, p), T, b)
+    plan = run_plan(torch, n, h, ndim, p, "fp64", variant)
+    out = plan.flux_div(to_dev(torch, T, torch.float64), to_dev(torch, b, torch.float64)).cpu().numpy()
+    assert rel_l1(out, ref) <= 1e-12
+    assert np.abs(out - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_flux_div_mixed(torch_cuda, name):
+    torch = torch_cuda
+    n, h, ndim, p, T, b = make_case(name)
+    print("flux_div mixed", name, n, flush=True)
+    b32 = b.astype(np.float32)
+    ref = oracle.flux_div(oracle_grid(n, h, ndim, p), T, b32.astype(np.float64))
+    plan = run_plan(torch, n, h, ndim, p, "mixed")
+    out = plan.flux_div(to_dev(torch, T, torch.float64), to_dev(torch, b32, torch.float32)).cpu().numpy()
+    assert rel_l1(out, ref) <= 1e-4
+
+
+def superstep_pair(torch, name, precision, steps, ratio, variant=-1):
+    n, h, ndim, p, T, b = make_case(name)
+    g = oracle_grid(n, h, ndim, p)
+    bg = b.astype(np.float32) if precision == "mixed" else b
+    bo = bg.astype(np.float64)
+    plan = run_plan(torch, n, h, ndim, p, precision, variant)
+    Td = to_dev(torch, T, torch.float64)
+    bd = to_dev(torch, bg, torch.float32 if precision == "mixed" else torch.float64)
+    To = T.copy()
+    for _ in range(steps):
+        dt = ratio * oracle.dt_par(g, To)
+        To, s_ref, _ = oracle.superstep(g, To, bo, dt)
+        s = plan.superstep(Td, bd, dt)
+        assert s == s_ref
+    return Td.cpu().numpy(), To, T
+
+
+@pytest.mark.parametrize("name,steps,ratio", [
+    ("gauss2d", 5, 50.0), ("tangled_mc", 2, inputs.midpoint_ratio(16)),
+    ("tangled_mc_sat", 2, inputs.midpoint_ratio(9)), ("iso1d", 3, 20.0),
+    ("flat2d_ragged", 2, 30.0), ("tiny3d", 2, inputs.midpoint_ratio(5)),
+])
+def test_superstep_fp64(torch_cuda, name, steps, ratio):
+    print("superstep fp64", name, steps, ratio, flush=True)
+    g, o, T0 = superstep_pair(torch_cuda, name, "fp64", steps, ratio)
+    assert rel_l1(g, o) <= 1e-12
+    # the change over the step is matched too, not only the background
+    assert rel_l1(g - T0, o - T0) <= 1e-10
+
+
+@pytest.mark.parametrize("name,steps,ratio", [
+    ("tangled_mc", 2, inputs.midpoint_ratio(16)), ("tangled_mc_sat", 2, inputs.midpoint_ratio(24)),
+    ("gauss2d", 5, 50.0), ("flat2d_ragged", 2, 30.0),
+])
+def test_superstep_mixed(torch_cuda, name, steps, ratio):
+    print("superstep mixed", name, steps, ratio, flush=True)
+    g, o, T0 = superstep_pair(torch_cuda, name, "mixed", steps, ratio)
+    err = rel_l1(g, o)
+    print("  rel-L1 %.3e  Linf %.3e" % (err, np.abs(g - o).max()))
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("variant", range(8))
+def test_superstep_every_variant(torch_cuda, variant):
+    print("variant", variant, flush=True)
+    g, o, _ = superstep_pair(torch_cuda, "tangled_mc_sat", "fp64", 1, inputs.midpoint_ratio(6), variant)
+    assert rel_l1(g, o) <= 1e-12
+
+
+def test_superstep_is_deterministic(torch_cuda):
+    torch = torch_cuda
+    n, h, ndim, p, T, b = make_case("tangled_mc")
+    plan = run_plan(torch, n, h, ndim, p, "fp64")
+    outs = []
+    for _ in range(2):
+        Td = to_dev(torch, T, torch.float64)
+        plan.superstep(Td, to_dev(torch, b, torch.float64), 1e-3)
+        outs.append(Td.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_superstep_conserves_energy_on_gpu(torch_cuda):
+    torch = torch_cuda
+    n, h, ndim, p, T, b = make_case("tangled_mc_sat")
+    plan = run_plan(torch, n, h, ndim, p, "fp64")
+    Td = to_dev(torch, T, torch.float64)
+    bd = to_dev(torch, b, torch.float64)
+    e0 = T.sum()
+    for _ in range(3):
+        s = plan.superstep(Td, bd, 40 * plan.dt_par(Td))
+    assert abs(Td.sum().item() - e0) <= 1e-13 * e0 * 3 * s
+
+
+def test_dt_par_and_stage_count_match_oracle(torch_cuda):
+    torch = torch_cuda
+    for name in CASES:
+        n, h, ndim, p, T, b = make_case(name)
+        plan = run_plan(torch, n, h, ndim, p, "fp64")
+        Td = to_dev(torch, T, torch.float64)
+        assert plan.dt_par(Td) == oracle.dt_par(oracle_grid(n, h, ndim, p), T)
+
+
+def test_flags_and_errors(torch_cuda):
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    n, h, ndim, p, T, b = make_case("tiny3d")
+    plan = rkl.Plan([lib_desc(n, h, ndim, p)], smax=8)
+    Td = to_dev(torch, T, torch.float64)
+    bd = to_dev(torch, b, torch.float64)
+    # stage count above smax: error, T untouched
+    with pytest.raises(rkl.RklError) as e:
+        plan.superstep(Td, bd, 1000 * plan.dt_par(Td))
+    assert e.value.status == rkl.RKL_ESTAGES
+    assert np.array_equal(Td.cpu().numpy(), T)
+    s, dtp, fl = plan.query()
+    assert fl & rkl.RKL_FLAG_STAGES
+    # a tiny super-step still takes the minimum two stages
+    assert plan.superstep(Td, bd, 1e-12) == 2
+    # non-positive and non-finite temperatures are flagged
+    T2 = T.copy()
+    T2[0, 0, 0] = -1.0
+    plan.superstep(to_dev(torch, T2, torch.float64), bd, 1e-6)
+    assert plan.query()[2] & rkl.RKL_FLAG_NONPOS
+    T2[0, 0, 0] = np.nan
+    plan.flux_div(to_dev(torch, T2, torch.float64), bd)
+    assert plan.query()[2] & rkl.RKL_FLAG_NONFINITE
+    with pytest.raises(ValueError):
+        plan.superstep(Td[:-1].clone(), bd, 1e-6)
+    with pytest.raises(TypeError):
+        plan.superstep(Td.float(), bd, 1e-6)
+    with pytest.raises(rkl.RklError):
+        plan.superstep(Td, bd, float("nan"))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_spitzer_256_sampled_full_size(torch_cuda, precision, tol):
+    """256^3 tangled field, kappa = T^2.5, kappa_perp = 1e-3, MC, s = 16: one
+    full-size super-step on the GPU against the oracle at sampled cells."""
+    torch = torch_cuda
+    w = inputs.spitzer_256()
+    g = oracle_grid(w.n, w.h, 3, w.params)
+    dt = w.ratio * oracle.dt_par(g, w.T)
+    bg = w.b.astype(np.float32) if precision == "mixed" else w.b
+    plan = run_plan(torch, w.n, w.h, 3, w.params, precision)
+    Td = to_dev(torch, w.T, torch.float64)
+    s = plan.superstep(Td, to_dev(torch, bg, torch.float32 if precision == "mixed" else torch.float64), dt)
+    assert s == oracle.stages(w.ratio) == 16
+    rng = np.random.default_rng(5)
+    centers = [tuple(int(v) for v in rng.integers(0, 256, 3)) for _ in range(6)] + [(0, 0, 0), (255, 255, 255)]
+    ref = sampled_superstep(w.T, bg.astype(np.float64), w.params, w.h, s, dt, centers)
+    got = Td.cpu().numpy()[tuple(np.array(centers).T)]
+    T0 = w.T[tuple(np.array(centers).T)]
+    assert np.abs(got - ref).max() <= tol * 4
+    assert rel_l1(got - T0, ref - T0) <= (1e-9 if precision == "fp64" else 1e-2)
