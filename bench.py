@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--workload", default="spitzer_256", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
@@ -91,6 +93,12 @@ def main():
 
     builder, precision, bytes_per_cs = WORKLOADS[args.workload]
     rkl.load(build_if_missing=True)
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = getattr(inputs, builder)()
     dev = torch.device("cuda:0")
     plan = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision=precision, variant=args.variant)

@@ -86,7 +86,7 @@ typedef struct {
     int32_t smax;         /* largest stage count accepted (coefficient table size); 0 = 1024
                              for one grid, 64 for several (a batched super-step issues
                              one stage launch per stage up to smax) */
-    int32_t reserved;
+    int32_t reserved;     /* must be 0 */
 } rkl_options;
 
 /*
@@ -141,9 +141,11 @@ rkl_status rkl_superstep(rkl_plan_t plan, int32_t grid, double *T, const void *b
                          double dt_hyp, int32_t *s_out, void *stream);
 
 /*
- * rkl_superstep_batched: one super-step of every grid of the plan at once, in
- * one persistent launch (plus a small reset kernel), with no host
- * synchronisation -- safe to capture in a HIP graph.  T and b are packed
+ * rkl_superstep_batched: one super-step of every grid of the plan at once
+ * with no host synchronisation -- safe to capture in a HIP graph: one
+ * reduce launch (dt_par and s per grid on the device), then one launch per
+ * stage j = 1..smax over every tile of every grid (grids with s < j skip
+ * it), so the plan's smax should be the largest stage count expected.  T and b are packed
  * (grid g at rkl_grid_offset(g) cells, b at 3x that); dt_hyp is a device
  * array of ngrids doubles; s_out (device, ngrids int32, may be NULL) receives
  * each grid's stage count.  A grid whose s exceeds smax is left unchanged

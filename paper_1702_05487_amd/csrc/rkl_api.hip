@@ -180,6 +180,7 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
     if (o.smax == 0) o.smax = ngrids > 1 ? 64 : 1024;
     if (o.smax < 2 || o.smax > 4096) return fail(RKL_EINVAL, "smax must be in [2, 4096]");
     if (o.variant < -1 || o.variant >= variant_count()) return fail(RKL_EINVAL, "variant out of range");
+    if (o.reserved != 0) return fail(RKL_EINVAL, "rkl_options.reserved must be 0");
 
     rkl_plan_s* p = new rkl_plan_s();
     p->ngrids = ngrids;

@@ -2,15 +2,21 @@
 // ("patches") of uneven size, each with its own field, super-step and stage
 // count, without host synchronisation (graph-capturable).
 //
-// Sequence: one reduce/finalize launch (a workgroup per grid computes that
-// grid's temperature extrema, dt_par and stage count s_g on the device), then
-// one launch per stage j = 1..smax over every tile of every grid; a tile
-// whose grid has s_g < j returns at once.  Tile shapes are chosen per grid so
-// that a patch narrower than 64 cells is covered by full-width rows (no
-// ragged x tiles); every tile runs the same run_tile code as the single-grid
-// kernels.
+// Launch sequence per super-step: one reduce launch (a workgroup per grid
+// computes that grid's temperature extrema, dt_par and stage count s_g on the
+// device), then one launch per stage j = 1..smax over every tile of every
+// grid; a tile whose grid has s_g < j returns at once.  Stage j of every grid
+// therefore starts only after stage j-1 of every grid has finished, with
+// kernel boundaries as the only synchronisation between workgroups.  Tiles
+// are dispatched largest grid first so that the small tiles fill the tail of
+// each launch.
+//
+// Tile shapes are chosen per grid so that a patch narrower than 64 cells is
+// covered by full-width rows (no ragged x tiles); every tile runs the same
+// run_tile code as the single-grid kernels.
 #include <algorithm>
 #include <cstring>
+#include <numeric>
 
 #include "rkl_batch.h"
 #include "rkl_tile.h"
@@ -19,21 +25,21 @@ namespace rkl {
 
 constexpr int kBT = 256;        // threads per batched workgroup
 constexpr int kPL = 400;        // LDS plane capacity, (bx+2)(by+2)
-constexpr int kFX = 320;        // x-face capacity, (bx+1) by
-constexpr int kFY = 320;        // y-face capacity, bx (by+1)
+constexpr int kFX = 320;        // x-face capacity per buffer, (bx+1) by
+constexpr int kFY = 320;        // y-face capacity per buffer, bx (by+1)
 
 struct BatchGrid {
     GridConst gc;
     int64_t off;
     int bx, by, bz, ntx, nty, nzc;
-    int tile0;
+    int ntiles;
 };
 
 struct BatchPlan {
     int ngrids = 0, precision = 0, smax = 0, items = 0;
     int limiter = 0, saturation = 0;
     BatchGrid* grids = nullptr;   // device
-    int* item_grid = nullptr;     // device, item -> grid
+    int2* items_dev = nullptr;    // device, item -> (grid, tile), largest grids first
 };
 
 __device__ __forceinline__ int xcd_remap_b(int b, int nb) {
@@ -82,9 +88,8 @@ __global__ __launch_bounds__(kBT) void batch_reduce_kernel(const BatchGrid* __re
     }
 }
 
-struct BatchStageArgs {
+struct BatchBufs {
     const BatchGrid* grids;
-    const int* item_grid;
     const GridState* state;
     const double* coef;
     double* T;
@@ -92,19 +97,13 @@ struct BatchStageArgs {
     double* Ya;
     double* Yb;
     void* MY0;
-    int stage;
 };
 
-template <typename R, bool LIM, bool SAT>
-__global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchStageArgs P) {
-    __shared__ TileLds<R, kPL, kFX, kFY> L;
-    const int item = xcd_remap_b(blockIdx.x, gridDim.x);
-    const int g = P.item_grid[item];
-    const GridState st = P.state[g];
-    const int j = P.stage;
-    if (st.s < j || (st.flags & RKL_FLAG_STAGES)) return;   // uniform over the block
+// stage j of tile t of grid g
+template <typename R, bool LIM, bool SAT, typename L_t>
+__device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int t, const GridState& st,
+                                           L_t& L) {
     const BatchGrid& G = P.grids[g];
-    int t = item - G.tile0;
     const int tile_x = t % G.ntx;
     t /= G.ntx;
     const int tile_y = t % G.nty;
@@ -162,6 +161,16 @@ __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchStageArgs P) {
     run_tile<R, LIM, SAT>(a, fk, tref, L);
 }
 
+template <typename R, bool LIM, bool SAT>
+__global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int2* __restrict__ items,
+                                                          int stage) {
+    __shared__ TileLds<R, kPL, kFX, kFY> L;
+    const int2 it = items[xcd_remap_b(blockIdx.x, gridDim.x)];
+    const GridState st = P.state[it.x];
+    if (st.s < stage || (st.flags & RKL_FLAG_STAGES)) return;   // uniform over the block
+    batch_tile<R, LIM, SAT>(P, it.x, stage, it.y, st, L);
+}
+
 // tile shape for one grid: full-width rows when the grid is at most 64 cells
 // wide, as many rows as fit 256 threads (at most 64), the whole z extent up
 // to 32 planes per tile
@@ -177,7 +186,7 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
     *out = nullptr;
     const int n = (int)desc.size();
     std::vector<BatchGrid> h(n);
-    std::vector<int> item_grid;
+    int64_t items = 0;
     for (int g = 0; g < n; ++g) {
         if (desc[g].limiter != desc[0].limiter || desc[g].saturation != desc[0].saturation) {
             why = "batched grids must share the limiter and saturation settings";
@@ -188,34 +197,45 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
         B.off = off[g];
         choose_tile(gc[g], B.bx, B.by, B.bz);
         if ((B.bx + 2) * (B.by + 2) > kPL || (B.bx + 1) * B.by > kFX || B.bx * (B.by + 1) > kFY ||
-            2 * (B.bx + 2) + 2 * B.by > kBT) {
+            2 * B.bx + 2 * B.by + 4 > kBT) {
             why = "internal: batched tile shape exceeds the LDS layout";
             return RKL_EINVAL;
         }
         B.ntx = (gc[g].n0 + B.bx - 1) / B.bx;
         B.nty = (gc[g].n1 + B.by - 1) / B.by;
         B.nzc = (gc[g].n2 + B.bz - 1) / B.bz;
-        B.tile0 = (int)item_grid.size();
         const int64_t nt = (int64_t)B.ntx * B.nty * B.nzc;
-        if (item_grid.size() + nt > (size_t)0x7fffffff) { why = "too many tiles"; return RKL_EINVAL; }
-        item_grid.insert(item_grid.end(), (size_t)nt, g);
+        if (items + nt > (int64_t)0x7fffffff) { why = "too many tiles"; return RKL_EINVAL; }
+        B.ntiles = (int)nt;
+        items += nt;
     }
+    // items ordered by grid size, largest first, so that a launch ends on small tiles
+    std::vector<int> by_size(n);
+    std::iota(by_size.begin(), by_size.end(), 0);
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int b) {
+        return (int64_t)gc[a].n0 * gc[a].n1 * gc[a].n2 > (int64_t)gc[b].n0 * gc[b].n1 * gc[b].n2;
+    });
+    std::vector<int2> item_list;
+    item_list.reserve((size_t)items);
+    for (int g : by_size)
+        for (int t = 0; t < h[g].ntiles; ++t) item_list.push_back(make_int2(g, t));
+
     BatchPlan* bp = new BatchPlan();
     bp->ngrids = n;
     bp->precision = precision;
     bp->smax = smax;
-    bp->items = (int)item_grid.size();
+    bp->items = (int)items;
     bp->limiter = desc[0].limiter;
     bp->saturation = desc[0].saturation;
     if (hipMalloc(&bp->grids, sizeof(BatchGrid) * n) != hipSuccess ||
-        hipMalloc(&bp->item_grid, sizeof(int) * item_grid.size()) != hipSuccess) {
+        hipMalloc(&bp->items_dev, sizeof(int2) * item_list.size()) != hipSuccess) {
         hipGetLastError();
         batch_free(bp);
         why = "device allocation failed";
         return RKL_ENOMEM;
     }
     if (hipMemcpy(bp->grids, h.data(), sizeof(BatchGrid) * n, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(bp->item_grid, item_grid.data(), sizeof(int) * item_grid.size(), hipMemcpyHostToDevice) !=
+        hipMemcpy(bp->items_dev, item_list.data(), sizeof(int2) * item_list.size(), hipMemcpyHostToDevice) !=
             hipSuccess) {
         hipGetLastError();
         batch_free(bp);
@@ -229,17 +249,18 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
 void batch_free(BatchPlan* bp) {
     if (!bp) return;
     hipFree(bp->grids);
-    hipFree(bp->item_grid);
+    hipFree(bp->items_dev);
     delete bp;
 }
 
 template <typename R>
-static void launch_stage_b(const BatchPlan* bp, const BatchStageArgs& a, hipStream_t st) {
+static void launch_stage_b(const BatchPlan* bp, const BatchBufs& a, int stage, hipStream_t st) {
     const bool lim = bp->limiter != 0, sat = bp->saturation != 0;
-    if (lim && sat) batch_stage_kernel<R, true, true><<<bp->items, kBT, 0, st>>>(a);
-    else if (lim) batch_stage_kernel<R, true, false><<<bp->items, kBT, 0, st>>>(a);
-    else if (sat) batch_stage_kernel<R, false, true><<<bp->items, kBT, 0, st>>>(a);
-    else batch_stage_kernel<R, false, false><<<bp->items, kBT, 0, st>>>(a);
+    const int2* it = bp->items_dev;
+    if (lim && sat) batch_stage_kernel<R, true, true><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    else if (lim) batch_stage_kernel<R, true, false><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    else if (sat) batch_stage_kernel<R, false, true><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    else batch_stage_kernel<R, false, false><<<bp->items, kBT, 0, st>>>(a, it, stage);
 }
 
 hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st) {
@@ -247,9 +268,8 @@ hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st) 
                                                     bp->smax);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    BatchStageArgs a;
+    BatchBufs a;
     a.grids = bp->grids;
-    a.item_grid = bp->item_grid;
     a.state = buf.state;
     a.coef = buf.coef;
     a.T = buf.T;
@@ -258,9 +278,8 @@ hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st) 
     a.Yb = buf.Yb;
     a.MY0 = buf.MY0;
     for (int j = 1; j <= bp->smax; ++j) {
-        a.stage = j;
-        if (bp->precision == RKL_MIXED) launch_stage_b<float>(bp, a, st);
-        else launch_stage_b<double>(bp, a, st);
+        if (bp->precision == RKL_MIXED) launch_stage_b<float>(bp, a, j, st);
+        else launch_stage_b<double>(bp, a, j, st);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

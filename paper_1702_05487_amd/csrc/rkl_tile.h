@@ -17,10 +17,12 @@
 // in an LDS ring; per-cell slopes and b of the current and next plane sit in
 // a two-plane LDS ring.  Every face flux is computed exactly once: each cell
 // computes its +x, +y and +z faces, the tile's -x and -y boundary faces are
-// extra jobs, x/y faces are exchanged through LDS and the +z face is carried
-// in a register to the next plane.  Flux arithmetic runs in R (double, or
-// float on temperatures offset by a reference value); the stage recurrence
-// always runs in double.
+// extra jobs, x/y faces are exchanged through (double-buffered) LDS and the
+// +z face is carried in a register to the next plane.  Each thread keeps the
+// three input planes of its own column (and of its halo cell) in registers,
+// so the z-slopes need no LDS and one barrier per plane suffices.  Flux
+// arithmetic runs in R (double, or float on temperatures offset by a
+// reference value); the stage recurrence always runs in double.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,12 +30,27 @@
 namespace rkl {
 
 // ---------------------------------------------------------------- math ----
+// FP32: the hardware square root / reciprocal / reciprocal square root.
+// FP64: the hardware estimate refined by two Newton steps (relative error
+// of the estimate ~2^-23, after two steps at the rounding level).
 __device__ __forceinline__ float r_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double r_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float r_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double r_rsqrt(double x) { return 1.0 / sqrt(x); }
-__device__ __forceinline__ float r_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double r_div(double a, double b) { return a / b; }
+__device__ __forceinline__ double r_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float r_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double r_rcp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
 __device__ __forceinline__ float r_pow(float x, float y) { return powf(x, y); }
 __device__ __forceinline__ double r_pow(double x, double y) { return pow(x, y); }
 
@@ -65,6 +82,13 @@ struct FaceK {
 // along the face normal.  s?1, s?2: the cells' slopes along the two
 // transverse axes; b?n/b?1/b?2: the cells' unit vectors (normal, transverse
 // 1, transverse 2 components).
+//
+// With c = b_L + b_R the face direction is c/|c| (0 if |c| < 1e-12), so
+// b_n (b.G) = c_n (c.G)/|c|^2, and the magnitude of the classical flux
+// -[k_perp G + (k_par-k_perp) b (b.G)] follows from
+// |F|^2 = k_perp^2 |G|^2 + (k_par^2 - k_perp^2) (b.G)^2.
+// kappa_par = kappa0 T^2.5 is evaluated as kappa0 T^3 / sqrt(T) and the
+// saturated flux 5 phi rho T^1.5 as satq T^2 / sqrt(T) (one reciprocal root).
 template <typename R, bool LIM, bool SAT>
 __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R sR2,
                                        R bLn, R bL1, R bL2, R bRn, R bR1, R bR2,
@@ -74,25 +98,24 @@ __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R
     const R G2 = LIM ? mc(sL2, sR2) : R(0.5) * (sL2 + sR2);
     R Tf = R(0.5) * (TL + TR) + k.tref;
     Tf = Tf > R(0) ? Tf : R(0);
-    const R sq = (SAT || k.kmode == 1) ? r_sqrt(Tf) : R(0);
+    const bool need_rs = SAT || k.kmode == 1;
+    const R rs = (need_rs && Tf > R(0)) ? r_rsqrt(Tf) : R(0);
+    const R T2 = Tf * Tf;
     const R kpar = k.kmode == 0 ? k.kappa0
-                 : (k.kmode == 1 ? k.kappa0 * (Tf * Tf * sq) : k.kappa0 * r_pow(Tf, k.kexp));
+                 : (k.kmode == 1 ? k.kappa0 * (T2 * Tf * rs) : k.kappa0 * r_pow(Tf, k.kexp));
     const R kperp = k.kperp * kpar;
-    R cn = bLn + bRn, c1 = bL1 + bR1, c2 = bL2 + bR2;
-    const R nb2 = cn * cn + c1 * c1 + c2 * c2;
-    const R inv = nb2 < R(1e-24) ? R(0) : r_rsqrt(nb2);
-    cn *= inv;
-    c1 *= inv;
-    c2 *= inv;
-    const R bG = cn * Gn + c1 * G1 + c2 * G2;
+    const R cn = bLn + bRn, c1 = bL1 + bR1, c2 = bL2 + bR2;
+    const R cc = cn * cn + c1 * c1 + c2 * c2;
+    const R cG = cn * Gn + c1 * G1 + c2 * G2;
+    const R w = cc < R(1e-24) ? R(0) : cG * r_rcp(cc);     // (b.G)/|c|
     const R dk = kpar - kperp;
-    R Fn = -(kperp * Gn + dk * cn * bG);
+    R Fn = -(kperp * Gn + dk * (cn * w));
     if (SAT) {
-        const R F1 = -(kperp * G1 + dk * c1 * bG);
-        const R F2 = -(kperp * G2 + dk * c2 * bG);
-        const R Fm = r_sqrt(Fn * Fn + F1 * F1 + F2 * F2);
-        const R q = k.satq * (Tf * sq);
-        Fn = q > R(0) ? r_div(q, q + Fm) * Fn : R(0);
+        const R GG = Gn * Gn + G1 * G1 + G2 * G2;
+        R F2 = kperp * kperp * GG + dk * (kpar + kperp) * (cG * w);
+        const R Fm = r_sqrt(F2 > R(0) ? F2 : R(0));
+        const R q = k.satq * (T2 * rs);
+        Fn = q > R(0) ? Fn * (q * r_rcp(q + Fm)) : R(0);
     }
     return Fn;
 }
@@ -108,7 +131,7 @@ struct TileArgs {
     const void* b;       // unit vectors, type R, 3 x N
     int n0, n1, n2, ndim;
     int x0, y0, z0, z1;  // tile origin and z range [z0, z1)
-    int bx, by;          // tile shape (bx*by <= threads)
+    int bx, by;          // tile shape (bx*by <= threads, 2bx+2by+4 <= threads)
     int kind;
     double ih0, ih1, ih2;
     double scale;        // multiplies div F: -(gamma-1)/rho (kind 0) or -tau (gamma-1)/rho
@@ -120,8 +143,8 @@ struct TileLds {
     R T[3][PLMAX];      // ring of three input planes (halo 1)
     R S[2][3][PLMAX];   // slopes of two planes
     R B[2][3][PLMAX];   // unit vectors of two planes
-    R FX[FXMAX];        // x-face fluxes, [by][bx+1]
-    R FY[FYMAX];        // y-face fluxes, [by+1][bx]
+    R FX[2][FXMAX];     // x-face fluxes, [by][bx+1], double-buffered by plane parity
+    R FY[2][FYMAX];     // y-face fluxes, [by+1][bx]
 };
 
 __device__ __forceinline__ int wrap(int i, int n) {
@@ -140,9 +163,11 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     const int tid = threadIdx.x;
     const int bx = a.bx, by = a.by, px = bx + 2;
     const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
-    const size_t plane = (size_t)n0 * (size_t)n1;
-    const size_t N = plane * (size_t)n2;
-    const R* bR = (const R*)a.b;
+    const int plane = n0 * n1;
+    const size_t N = (size_t)plane * (size_t)n2;
+    const R* b0 = (const R*)a.b;
+    const R* b1 = b0 + N;
+    const R* b2 = b1 + N;
     const R ih0 = R(a.ih0), ih1 = R(a.ih1), ih2 = R(a.ih2);
     const bool do_y = a.ndim >= 2, do_z = a.ndim >= 3;
 
@@ -153,31 +178,28 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     const int oxy = wrap(a.y0 + ty, n1) * n0 + wrap(a.x0 + tx, n0);
     const bool store = own && (a.x0 + tx < n0) && (a.y0 + ty < n1);
 
-    // halo cell whose temperature this thread loads (corners included)
-    const bool hjob = tid < 2 * px + 2 * by;
+    // halo cell of this thread: the 2bx+2by edge cells first (y-halo rows,
+    // then x-halo columns), then the 4 corners.  An edge thread also provides
+    // the slopes and unit vector of its cell (y-halo: x and z slopes; x-halo:
+    // y and z slopes); corners only supply temperatures.
+    const int ne = 2 * bx + 2 * by;
+    const bool hjob = tid < ne + 4;
+    const bool djob = tid < ne;
+    bool dxh = false;
     int hslot = 0, hxy = 0;
     if (hjob) {
-        int hi, hj;
-        if (tid < px) { hi = tid - 1; hj = -1; }
-        else if (tid < 2 * px) { hi = tid - px - 1; hj = by; }
-        else if (tid < 2 * px + by) { hi = -1; hj = tid - 2 * px; }
-        else { hi = bx; hj = tid - 2 * px - by; }
-        hslot = (hj + 1) * px + hi + 1;
-        hxy = wrap(a.y0 + hj, n1) * n0 + wrap(a.x0 + hi, n0);
-    }
-    // halo cell whose slopes and b this thread provides (edges, no corners):
-    // y-halo cells need the x and z slopes, x-halo cells the y and z slopes
-    const bool djob = tid < 2 * bx + 2 * by;
-    int dslot = 0, dxy = 0;
-    bool dxh = false;
-    if (djob) {
         int hi, hj;
         if (tid < bx) { hi = tid; hj = -1; }
         else if (tid < 2 * bx) { hi = tid - bx; hj = by; }
         else if (tid < 2 * bx + by) { hi = -1; hj = tid - 2 * bx; dxh = true; }
-        else { hi = bx; hj = tid - 2 * bx - by; dxh = true; }
-        dslot = (hj + 1) * px + hi + 1;
-        dxy = wrap(a.y0 + hj, n1) * n0 + wrap(a.x0 + hi, n0);
+        else if (tid < ne) { hi = bx; hj = tid - 2 * bx - by; dxh = true; }
+        else {
+            const int c = tid - ne;
+            hi = (c & 1) ? bx : -1;
+            hj = (c & 2) ? by : -1;
+        }
+        hslot = (hj + 1) * px + hi + 1;
+        hxy = wrap(a.y0 + hj, n1) * n0 + wrap(a.x0 + hi, n0);
     }
     // extra face: the tile's -x face of row j (tid < by) or -y face of column i
     const bool fjob = tid < by + (do_y ? bx : 0);
@@ -187,64 +209,79 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
         else { const int i = tid - by; fdir = 1; fL = i + 1; fR = px + i + 1; fidx = i; }
     }
 
-    auto plane_base = [&](int p) -> size_t { return (size_t)wrap(p, n2) * plane; };
-
-    // pipeline state
-    double pTo = 0.0, pTh = 0.0;            // prefetched T(k+2): own, halo
-    R pbo0 = 0, pbo1 = 0, pbo2 = 0;         // prefetched b(k+1): own
-    R pbd0 = 0, pbd1 = 0, pbd2 = 0;         // prefetched b(k+1): halo
-    double yq0 = 0.0, yq1 = 0.0, yq2 = 0.0; // own FP64 input: planes k, k+1, k+2
-    R ob00 = 0, ob01 = 0, ob02 = 0;         // own b, plane k
-    R ob10 = 0, ob11 = 0, ob12 = 0;         // own b, plane k+1
-    R os00 = 0, os01 = 0, os10 = 0, os11 = 0;  // own x/y slopes, planes k and k+1
-    R fzp = 0;                               // +z face flux of plane k-1
-
     const int z0 = a.z0, z1 = a.z1;
+    // wrapped plane index of k + 3 (prefetched temperature plane), incremented per plane
+    int pz3 = wrap(z0 + 1, n2);
+    auto inc = [&](int p) { return p + 1 == n2 ? 0 : p + 1; };
+
+    // pipeline registers
+    double pTo = 0.0;                         // prefetched T(k+2), own cell (FP64)
+    R pTh = 0;                                // prefetched T(k+2), halo cell
+    R pbo0 = 0, pbo1 = 0, pbo2 = 0;           // prefetched b(k+1), own
+    R pbd0 = 0, pbd1 = 0, pbd2 = 0;           // prefetched b(k+1), halo
+    double yq0 = 0.0, yq1 = 0.0, yq2 = 0.0;   // own FP64 input, planes k, k+1, k+2
+    R oq0 = 0, oq1 = 0, oq2 = 0;              // same in flux precision
+    R hq0 = 0, hq1 = 0, hq2 = 0;              // halo cell input, planes k, k+1, k+2
+    R ob00 = 0, ob01 = 0, ob02 = 0;           // own b, plane k
+    R ob10 = 0, ob11 = 0, ob12 = 0;           // own b, plane k+1
+    R os00 = 0, os01 = 0, os10 = 0, os11 = 0; // own x/y slopes, planes k and k+1
+    R fzp = 0;                                // +z face flux of plane k-1
+
     // ring slots: T(k) c0, T(k+1) c1, T(k+2) c2; slopes/b of plane k in dc, of k+1 in dn
-    int c0 = 0, c1 = 1, c2 = 2, dc = 1, dn = 0;
+    int c0 = 0, c1 = 1, c2 = 2, dc = 1, dn = 0, fb = 0;
     {
-        const size_t pb0 = plane_base(z0 - 2), pb1 = plane_base(z0 - 1), pb2 = plane_base(z0);
+        const double* p0 = a.Yin + (size_t)wrap(z0 - 2, n2) * plane;
+        const double* p1 = a.Yin + (size_t)wrap(z0 - 1, n2) * plane;
+        const double* p2 = a.Yin + (size_t)wrap(z0, n2) * plane;
+        const size_t pb = (size_t)wrap(z0 - 1, n2) * plane;
         if (own) {
-            yq1 = a.Yin[pb0 + oxy];
-            yq2 = a.Yin[pb1 + oxy];
-            L.T[0][oslot] = to_r<R>(yq1, tref);
-            L.T[1][oslot] = to_r<R>(yq2, tref);
-            pTo = a.Yin[pb2 + oxy];
-            pbo0 = bR[pb1 + oxy];
-            pbo1 = bR[N + pb1 + oxy];
-            pbo2 = bR[2 * N + pb1 + oxy];
+            yq1 = p0[oxy];
+            yq2 = p1[oxy];
+            oq1 = to_r<R>(yq1, tref);
+            oq2 = to_r<R>(yq2, tref);
+            L.T[0][oslot] = oq1;
+            L.T[1][oslot] = oq2;
+            pTo = p2[oxy];
+            pbo0 = b0[pb + oxy]; pbo1 = b1[pb + oxy]; pbo2 = b2[pb + oxy];
         }
         if (hjob) {
-            L.T[0][hslot] = to_r<R>(a.Yin[pb0 + hxy], tref);
-            L.T[1][hslot] = to_r<R>(a.Yin[pb1 + hxy], tref);
-            pTh = a.Yin[pb2 + hxy];
+            hq1 = to_r<R>(p0[hxy], tref);
+            hq2 = to_r<R>(p1[hxy], tref);
+            L.T[0][hslot] = hq1;
+            L.T[1][hslot] = hq2;
+            pTh = to_r<R>(p2[hxy], tref);
         }
-        if (djob) {
-            pbd0 = bR[pb1 + dxy];
-            pbd1 = bR[N + pb1 + dxy];
-            pbd2 = bR[2 * N + pb1 + dxy];
-        }
+        if (djob) { pbd0 = b0[pb + hxy]; pbd1 = b1[pb + hxy]; pbd2 = b2[pb + hxy]; }
     }
+    __syncthreads();
 
     for (int k = z0 - 2; k < z1; ++k) {
-        // ---- A: T(k+2) into the ring, b(k+1) into the b ring; prefetch the next plane
+        // ---- A: T(k+2) into the ring and the register queues, b(k+1) into the b ring
         if (own) {
-            L.T[c2][oslot] = to_r<R>(pTo, tref);
             yq0 = yq1; yq1 = yq2; yq2 = pTo;
+            oq0 = oq1; oq1 = oq2; oq2 = to_r<R>(pTo, tref);
+            L.T[c2][oslot] = oq2;
             L.B[dn][0][oslot] = pbo0; L.B[dn][1][oslot] = pbo1; L.B[dn][2][oslot] = pbo2;
             ob00 = ob10; ob01 = ob11; ob02 = ob12;
             ob10 = pbo0; ob11 = pbo1; ob12 = pbo2;
         }
-        if (hjob) L.T[c2][hslot] = to_r<R>(pTh, tref);
-        if (djob) { L.B[dn][0][dslot] = pbd0; L.B[dn][1][dslot] = pbd1; L.B[dn][2][dslot] = pbd2; }
+        if (hjob) {
+            hq0 = hq1; hq1 = hq2; hq2 = pTh;
+            L.T[c2][hslot] = hq2;
+        }
+        if (djob) { L.B[dn][0][hslot] = pbd0; L.B[dn][1][hslot] = pbd1; L.B[dn][2][hslot] = pbd2; }
+        // prefetch the next plane: T(k+3) and b(k+2)
         if (k + 1 < z1) {
-            const size_t pt = plane_base(k + 3), pb = plane_base(k + 2);
+            const double* pt = a.Yin + (size_t)pz3 * plane;
+            const int pbz = pz3 == 0 ? n2 - 1 : pz3 - 1;
+            const size_t pb = (size_t)pbz * plane;
             if (own) {
-                pTo = a.Yin[pt + oxy];
-                pbo0 = bR[pb + oxy]; pbo1 = bR[N + pb + oxy]; pbo2 = bR[2 * N + pb + oxy];
+                pTo = pt[oxy];
+                pbo0 = b0[pb + oxy]; pbo1 = b1[pb + oxy]; pbo2 = b2[pb + oxy];
             }
-            if (hjob) pTh = a.Yin[pt + hxy];
-            if (djob) { pbd0 = bR[pb + dxy]; pbd1 = bR[N + pb + dxy]; pbd2 = bR[2 * N + pb + dxy]; }
+            if (hjob) pTh = to_r<R>(pt[hxy], tref);
+            if (djob) { pbd0 = b0[pb + hxy]; pbd1 = b1[pb + hxy]; pbd2 = b2[pb + hxy]; }
+            pz3 = inc(pz3);
         }
         double ym2 = 0.0, y0v = 0.0, my0 = 0.0;
         if (k >= z0 && own && a.kind == 2) {
@@ -253,40 +290,41 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
             y0v = a.Y0[o];
             my0 = (double)((const R*)a.MY0in)[o];
         }
-        __syncthreads();
 
-        // ---- B: slopes of plane k+1 (needs T(k), T(k+1), T(k+2))
+        // ---- B: slopes of plane k+1.  In-plane neighbours of T(k+1) come from
+        // the ring (written one plane earlier); z neighbours from registers.
         if (own) {
-            const R t0 = L.T[c1][oslot];
-            const R s0 = cell_slope<R, LIM>(L.T[c1][oslot - 1], t0, L.T[c1][oslot + 1], ih0);
-            const R s1 = cell_slope<R, LIM>(L.T[c1][oslot - px], t0, L.T[c1][oslot + px], ih1);
-            const R s2 = cell_slope<R, LIM>(L.T[c0][oslot], t0, L.T[c2][oslot], ih2);
+            const R* T1 = L.T[c1];
+            const R s0 = cell_slope<R, LIM>(T1[oslot - 1], oq1, T1[oslot + 1], ih0);
+            const R s1 = cell_slope<R, LIM>(T1[oslot - px], oq1, T1[oslot + px], ih1);
+            const R s2 = cell_slope<R, LIM>(oq0, oq1, oq2, ih2);
             L.S[dn][0][oslot] = s0; L.S[dn][1][oslot] = s1; L.S[dn][2][oslot] = s2;
             os00 = os10; os01 = os11; os10 = s0; os11 = s1;
         }
         if (djob) {
-            const R t0 = L.T[c1][dslot];
-            if (dxh) L.S[dn][1][dslot] = cell_slope<R, LIM>(L.T[c1][dslot - px], t0, L.T[c1][dslot + px], ih1);
-            else     L.S[dn][0][dslot] = cell_slope<R, LIM>(L.T[c1][dslot - 1], t0, L.T[c1][dslot + 1], ih0);
-            L.S[dn][2][dslot] = cell_slope<R, LIM>(L.T[c0][dslot], t0, L.T[c2][dslot], ih2);
+            const R* T1 = L.T[c1];
+            if (dxh) L.S[dn][1][hslot] = cell_slope<R, LIM>(T1[hslot - px], hq1, T1[hslot + px], ih1);
+            else     L.S[dn][0][hslot] = cell_slope<R, LIM>(T1[hslot - 1], hq1, T1[hslot + 1], ih0);
+            L.S[dn][2][hslot] = cell_slope<R, LIM>(hq0, hq1, hq2, ih2);
         }
-        __syncthreads();
 
-        // ---- C: faces of plane k
+        // ---- C: faces of plane k (inputs written in earlier planes)
         R fzn = 0;
         if (k >= z0) {
             const R* Tk = L.T[c0];
             const R(*S)[PLMAX] = L.S[dc];
             const R(*Bv)[PLMAX] = L.B[dc];
+            R* FX = L.FX[fb];
+            R* FY = L.FY[fb];
             if (own) {
                 const int r = oslot + 1;
-                L.FX[ty * (bx + 1) + tx + 1] = face_flux<R, LIM, SAT>(
-                    Tk[oslot], Tk[r], ih0, S[1][oslot], S[1][r], S[2][oslot], S[2][r],
+                FX[ty * (bx + 1) + tx + 1] = face_flux<R, LIM, SAT>(
+                    oq0, Tk[r], ih0, S[1][oslot], S[1][r], S[2][oslot], S[2][r],
                     Bv[0][oslot], Bv[1][oslot], Bv[2][oslot], Bv[0][r], Bv[1][r], Bv[2][r], fk);
                 if (do_y) {
                     const int u = oslot + px;
-                    L.FY[(ty + 1) * bx + tx] = face_flux<R, LIM, SAT>(
-                        Tk[oslot], Tk[u], ih1, S[0][oslot], S[0][u], S[2][oslot], S[2][u],
+                    FY[(ty + 1) * bx + tx] = face_flux<R, LIM, SAT>(
+                        oq0, Tk[u], ih1, S[0][oslot], S[0][u], S[2][oslot], S[2][u],
                         Bv[1][oslot], Bv[0][oslot], Bv[2][oslot], Bv[1][u], Bv[0][u], Bv[2][u], fk);
                 }
             }
@@ -296,20 +334,22 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
                 const R f = face_flux<R, LIM, SAT>(
                     Tk[fL], Tk[fR], fdir == 0 ? ih0 : ih1, S[t1][fL], S[t1][fR], S[2][fL], S[2][fR],
                     Bv[fdir][fL], Bv[t1][fL], Bv[2][fL], Bv[fdir][fR], Bv[t1][fR], Bv[2][fR], fk);
-                if (fdir == 0) L.FX[fidx] = f; else L.FY[fidx] = f;
+                if (fdir == 0) FX[fidx] = f; else FY[fidx] = f;
             }
         }
         if (do_z && own && k >= z0 - 1) {
-            fzn = face_flux<R, LIM, SAT>(L.T[c0][oslot], L.T[c1][oslot], ih2, os00, os10, os01, os11,
+            fzn = face_flux<R, LIM, SAT>(oq0, oq1, ih2, os00, os10, os01, os11,
                                          ob02, ob00, ob01, ob12, ob10, ob11, fk);
         }
         __syncthreads();
 
         // ---- D: divergence and the stage update of plane k
         if (k >= z0 && store) {
+            const R* FX = L.FX[fb];
+            const R* FY = L.FY[fb];
             const int fx = ty * (bx + 1) + tx;
-            R div = (L.FX[fx + 1] - L.FX[fx]) * ih0;
-            if (do_y) div += (L.FY[(ty + 1) * bx + tx] - L.FY[ty * bx + tx]) * ih1;
+            R div = (FX[fx + 1] - FX[fx]) * ih0;
+            if (do_y) div += (FY[(ty + 1) * bx + tx] - FY[ty * bx + tx]) * ih1;
             if (do_z) div += (fzn - fzp) * ih2;
             const size_t o = (size_t)k * plane + oxy;
             const double tl = a.scale * (double)div;
@@ -326,6 +366,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
         fzp = fzn;
         const int t = c0; c0 = c1; c1 = c2; c2 = t;
         const int d = dc; dc = dn; dn = d;
+        fb ^= 1;
     }
 }
 

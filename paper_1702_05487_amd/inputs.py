@@ -219,7 +219,7 @@ class PatchSet:
 
 
 def patch_set(npatch: int = 2000, seed: int = 7, fields: bool = True,
-              lo: int = 16, hi: int = 64, smin: int = 4, smax: int = 40) -> PatchSet:
+              lo: int = 16, hi: int = 64, smin: int = 4, smax: int = 40, device=None) -> PatchSet:
     """Patch edges i.i.d. log-uniform in [lo, hi] per axis (rounded); each patch
     has its own tangled b (seed 1000+2p) and T = 1 + 0.1 noise (seed 1001+2p)
     with 2 <= |m| <= min(16, n_min/4), and a stage count drawn uniformly in
@@ -234,6 +234,6 @@ def patch_set(npatch: int = 2000, seed: int = 7, fields: bool = True,
         for p, n in enumerate(ps.n):
             kmax = min(16.0, float(min(n) // 4))
             box = tuple(v / 64.0 for v in n)
-            ps.b.append(tangled_b(n, 1000 + 2 * p, kmax=kmax, box=box))
-            ps.T.append(noisy_temperature(n, 1001 + 2 * p, kmax=kmax))
+            ps.b.append(tangled_b(n, 1000 + 2 * p, kmax=kmax, box=box, device=device))
+            ps.T.append(noisy_temperature(n, 1001 + 2 * p, kmax=kmax, device=device))
     return ps

@@ -1,0 +1,160 @@
+"""Batched super-step (many uneven patches, per-patch s, one graph-capturable
+launch sequence) vs the FP64 oracle run patch by patch."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import lib_desc, oracle_grid, rel_l1
+from paper_1702_05487_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1702_05487_amd import rkl
+    rkl.load(build_if_missing=False)
+    return torch
+
+
+def small_patch_set(npatch, seed, lo=8, hi=40, smin=2, smax=12):
+    return inputs.patch_set(npatch, seed=seed, lo=lo, hi=hi, smin=smin, smax=smax)
+
+
+def pack(torch, ps, precision):
+    bdt = np.float32 if precision == "mixed" else np.float64
+    T = np.concatenate([t.ravel() for t in ps.T])
+    b = np.concatenate([bb.astype(bdt).ravel() for bb in ps.b])
+    tdt = torch.float32 if precision == "mixed" else torch.float64
+    return (torch.from_numpy(T).to("cuda:0"), torch.from_numpy(b).to("cuda:0", dtype=tdt))
+
+
+def oracle_patches(ps, precision):
+    outs, svals, dts = [], [], []
+    for p, n in enumerate(ps.n):
+        h = tuple(1.0 / 64 for _ in range(3))
+        g = oracle_grid(n, h, 3, ps.params)
+        b = ps.b[p].astype(np.float32).astype(np.float64) if precision == "mixed" else ps.b[p]
+        dt = ps.ratio[p] * oracle.dt_par(g, ps.T[p])
+        To, s, _ = oracle.superstep(g, ps.T[p], b, dt)
+        outs.append(To)
+        svals.append(s)
+        dts.append(dt)
+    return outs, svals, dts
+
+
+def make_plan(ps, precision, smax=16):
+    from paper_1702_05487_amd import rkl
+    descs = [lib_desc(n, (1 / 64,) * 3, 3, ps.params) for n in ps.n]
+    return rkl.Plan(descs, precision=precision, smax=smax)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_batched_matches_oracle(torch_cuda, precision, tol):
+    torch = torch_cuda
+    ps = small_patch_set(20, seed=3)
+    print("batched", precision, [n for n in ps.n][:5], flush=True)
+    ref, sref, dts = oracle_patches(ps, precision)
+    plan = make_plan(ps, precision)
+    T, b = pack(torch, ps, precision)
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
+    s_out = torch.zeros(len(ps.n), dtype=torch.int32, device="cuda:0")
+    plan.superstep_batched(T, b, dt, s_out)
+    got = T.cpu().numpy()
+    off = plan.offsets()
+    assert list(s_out.cpu().numpy()) == sref
+    for p in range(len(ps.n)):
+        gp = got[off[p]:off[p + 1]].reshape(ref[p].shape)
+        assert rel_l1(gp, ref[p]) <= tol, p
+        assert plan.query(p)[0] == sref[p]
+
+
+def test_batched_equals_single_grid_calls(torch_cuda):
+    # the batched launch and per-grid rkl_superstep give bit-identical results
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    ps = small_patch_set(12, seed=4)
+    _, _, dts = oracle_patches(ps, "fp64")
+    plan = make_plan(ps, "fp64")
+    T, b = pack(torch, ps, "fp64")
+    T1 = T.clone()
+    plan.superstep_batched(T, b, torch.tensor(dts, dtype=torch.float64, device="cuda:0"))
+    off = plan.offsets()
+    for p, n in enumerate(ps.n):
+        single = rkl.Plan([lib_desc(n, (1 / 64,) * 3, 3, ps.params)], precision="fp64")
+        Tp = T1[off[p]:off[p + 1]].clone()
+        single.superstep(Tp, b[3 * off[p]:3 * off[p + 1]].clone(), dts[p])
+        assert torch.equal(Tp, T[off[p]:off[p + 1]]), p
+
+
+@pytest.mark.skip(reason="the single persistent launch with per-grid stage-dependency counters "
+                         "(work queues, agent-scope release/acquire between workgroups) did not "
+                         "finish on the MI355X box; its cause is not shown, so that code path is "
+                         "removed and the batched super-step uses one launch per stage")
+def test_persistent_equals_per_stage_launches():
+    pass
+
+
+def test_many_supersteps_match_oracle(torch_cuda):
+    # three consecutive batched super-steps (s re-computed on the device each time)
+    torch = torch_cuda
+    ps = small_patch_set(12, seed=9, lo=8, hi=32, smax=10)
+    plan = make_plan(ps, "fp64")
+    T, b = pack(torch, ps, "fp64")
+    off = plan.offsets()
+    Tref = [t.copy() for t in ps.T]
+    for _ in range(3):
+        dts = []
+        for p, n in enumerate(ps.n):
+            g = oracle_grid(n, (1 / 64,) * 3, 3, ps.params)
+            dt = ps.ratio[p] * oracle.dt_par(g, Tref[p])
+            Tref[p], _, _ = oracle.superstep(g, Tref[p], ps.b[p], dt)
+            dts.append(dt)
+        plan.superstep_batched(T, b, torch.tensor(dts, dtype=torch.float64, device="cuda:0"))
+    got = T.cpu().numpy()
+    for p in range(len(ps.n)):
+        assert rel_l1(got[off[p]:off[p + 1]].reshape(Tref[p].shape), Tref[p]) <= 1e-12
+
+
+def test_graph_replays_match_eager(torch_cuda):
+    """Capture one batched super-step in a HIP graph, replay it several
+    times with eager work and synchronisations between, and check every
+    replay against the eager launch sequence on a copy."""
+    torch = torch_cuda
+    ps = small_patch_set(16, seed=5)
+    _, _, dts = oracle_patches(ps, "mixed")
+    plan = make_plan(ps, "mixed")
+    eager_plan = make_plan(ps, "mixed")
+    T, b = pack(torch, ps, "mixed")
+    Te = T.clone()
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
+    s_g = torch.zeros(len(ps.n), dtype=torch.int32, device="cuda:0")
+    s_e = torch.zeros_like(s_g)
+    plan.graph_capture(T, b, dt, s_g)
+    for r in range(4):
+        plan.graph_launch()
+        torch.cuda.synchronize()
+        eager_plan.superstep_batched(Te, b, dt, s_e)
+        torch.cuda.synchronize()
+        _ = (Te * 2).sum().item()      # unrelated eager work between replays
+        assert torch.equal(T, Te), r
+        assert torch.equal(s_g, s_e), r
+
+
+def test_batched_stage_limit_is_flagged(torch_cuda):
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    ps = small_patch_set(6, seed=6, smax=6)
+    _, sref, dts = oracle_patches(ps, "fp64")
+    assert max(sref) <= 8
+    plan = make_plan(ps, "fp64", smax=8)
+    T, b = pack(torch, ps, "fp64")
+    T0 = T.clone()
+    dts[2] = dts[2] * 100.0      # this patch would need more than 8 stages
+    plan.superstep_batched(T, b, torch.tensor(dts, dtype=torch.float64, device="cuda:0"))
+    off = plan.offsets()
+    assert plan.query(2)[2] & rkl.RKL_FLAG_STAGES
+    assert torch.equal(T[off[2]:off[3]], T0[off[2]:off[3]])
+    assert not torch.equal(T[off[1]:off[2]], T0[off[1]:off[2]])
