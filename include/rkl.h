@@ -190,6 +190,16 @@ rkl_status rkl_set_variant(rkl_plan_t plan, int32_t variant);
 rkl_status rkl_profile(rkl_plan_t plan, int32_t enable);
 rkl_status rkl_profile_read(rkl_plan_t plan, double *ms, int64_t *launches, int64_t *cell_stages);
 
+/*
+ * rkl_autotune: time every stencil variant (tile shape, z-chunk) on `grid`
+ * with the caller's fields -- `reps` super-steps of dt_hyp each, on a
+ * plan-owned scratch copy of T (T itself is not modified) -- select the
+ * fastest for the plan and return its index and average super-step time.
+ * Allocates a scratch copy of T for the duration of the call; synchronises.
+ */
+rkl_status rkl_autotune(rkl_plan_t plan, int32_t grid, const double *T, const void *b, double dt_hyp,
+                        int32_t reps, int32_t *best_variant, double *best_ms, void *stream);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *rkl_last_error(void);
 

@@ -344,6 +344,56 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
     return RKL_OK;
 }
 
+rkl_status rkl_autotune(rkl_plan_t p, int32_t g, const double* T, const void* b, double dt_hyp, int32_t reps,
+                        int32_t* best_variant, double* best_ms, void* stream) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if (reps < 1 || reps > 1000) return fail(RKL_EINVAL, "reps must be in [1, 1000]");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = sizeof(double) * (size_t)(p->off[g + 1] - p->off[g]);
+    double* W = nullptr;
+    HIPCHECK(hipMalloc(&W, bytes), "autotune scratch");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = -1;
+    float best_t = 0.f;
+    const int saved = p->variant;
+    const bool saved_prof = p->prof;
+    p->prof = false;
+    rkl_status res = RKL_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        res = fail(RKL_EDEVICE, "autotune events");
+    }
+    for (int v = 0; res == RKL_OK && v < variant_count(); ++v) {
+        p->variant = v;
+        // one untimed super-step from the caller's T, then reps timed ones
+        if (hipMemcpyAsync(W, T, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) { res = fail(RKL_EDEVICE, "autotune copy"); break; }
+        res = rkl_superstep(p, g, W, b, dt_hyp, nullptr, stream);
+        if (res != RKL_OK) break;
+        if (hipMemcpyAsync(W, T, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipEventRecord(e0, s) != hipSuccess) { res = fail(RKL_EDEVICE, "autotune copy"); break; }
+        for (int r = 0; r < reps && res == RKL_OK; ++r) res = rkl_superstep(p, g, W, b, dt_hyp, nullptr, stream);
+        if (res != RKL_OK) break;
+        float t = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) { res = fail(RKL_EDEVICE, "autotune timing"); break; }
+        if (best < 0 || t < best_t) { best = v; best_t = t; }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipStreamSynchronize(s);
+    hipFree(W);
+    p->prof = saved_prof;
+    if (res != RKL_OK) {
+        p->variant = saved;
+        return res;
+    }
+    p->variant = best;
+    if (best_variant) *best_variant = best;
+    if (best_ms) *best_ms = best_t / reps;
+    return RKL_OK;
+}
+
 rkl_status rkl_profile(rkl_plan_t p, int32_t enable) {
     if (!p) return fail(RKL_EINVAL, "plan is NULL");
     HIPCHECK(hipDeviceSynchronize(), "profile sync");

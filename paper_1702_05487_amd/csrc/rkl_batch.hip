@@ -37,7 +37,7 @@ struct BatchGrid {
 
 struct BatchPlan {
     int ngrids = 0, precision = 0, smax = 0, items = 0;
-    int limiter = 0, saturation = 0;
+    int limiter = 0, saturation = 0, kmode = 0;
     BatchGrid* grids = nullptr;   // device
     int2* items_dev = nullptr;    // device, item -> (grid, tile), largest grids first
 };
@@ -100,7 +100,7 @@ struct BatchBufs {
 };
 
 // stage j of tile t of grid g
-template <typename R, bool LIM, bool SAT, typename L_t>
+template <typename R, bool LIM, bool SAT, int KM, typename L_t>
 __device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int t, const GridState& st,
                                            L_t& L) {
     const BatchGrid& G = P.grids[g];
@@ -157,18 +157,17 @@ __device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int
     fk.kperp = R(G.gc.kperp);
     fk.satq = R(G.gc.satq);
     fk.tref = R(tref);
-    fk.kmode = G.gc.kmode;
-    run_tile<R, LIM, SAT>(a, fk, tref, L);
+    run_tile<R, LIM, SAT, KM>(a, fk, tref, L);
 }
 
-template <typename R, bool LIM, bool SAT>
+template <typename R, bool LIM, bool SAT, int KM>
 __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int2* __restrict__ items,
                                                           int stage) {
     __shared__ TileLds<R, kPL, kFX, kFY> L;
     const int2 it = items[xcd_remap_b(blockIdx.x, gridDim.x)];
     const GridState st = P.state[it.x];
     if (st.s < stage || (st.flags & RKL_FLAG_STAGES)) return;   // uniform over the block
-    batch_tile<R, LIM, SAT>(P, it.x, stage, it.y, st, L);
+    batch_tile<R, LIM, SAT, KM>(P, it.x, stage, it.y, st, L);
 }
 
 // tile shape for one grid: full-width rows when the grid is at most 64 cells
@@ -188,8 +187,10 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
     std::vector<BatchGrid> h(n);
     int64_t items = 0;
     for (int g = 0; g < n; ++g) {
-        if (desc[g].limiter != desc[0].limiter || desc[g].saturation != desc[0].saturation) {
-            why = "batched grids must share the limiter and saturation settings";
+        if (desc[g].limiter != desc[0].limiter || desc[g].saturation != desc[0].saturation ||
+            gc[g].kmode != gc[0].kmode) {
+            why = "batched grids must share the limiter and saturation settings and the kind of "
+                  "conductivity law (kappa_exp 0, 2.5 or other)";
             return RKL_EINVAL;
         }
         BatchGrid& B = h[g];
@@ -227,6 +228,7 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
     bp->items = (int)items;
     bp->limiter = desc[0].limiter;
     bp->saturation = desc[0].saturation;
+    bp->kmode = gc[0].kmode;
     if (hipMalloc(&bp->grids, sizeof(BatchGrid) * n) != hipSuccess ||
         hipMalloc(&bp->items_dev, sizeof(int2) * item_list.size()) != hipSuccess) {
         hipGetLastError();
@@ -253,14 +255,21 @@ void batch_free(BatchPlan* bp) {
     delete bp;
 }
 
-template <typename R>
-static void launch_stage_b(const BatchPlan* bp, const BatchBufs& a, int stage, hipStream_t st) {
+template <typename R, int KM>
+static void launch_stage_km(const BatchPlan* bp, const BatchBufs& a, int stage, hipStream_t st) {
     const bool lim = bp->limiter != 0, sat = bp->saturation != 0;
     const int2* it = bp->items_dev;
-    if (lim && sat) batch_stage_kernel<R, true, true><<<bp->items, kBT, 0, st>>>(a, it, stage);
-    else if (lim) batch_stage_kernel<R, true, false><<<bp->items, kBT, 0, st>>>(a, it, stage);
-    else if (sat) batch_stage_kernel<R, false, true><<<bp->items, kBT, 0, st>>>(a, it, stage);
-    else batch_stage_kernel<R, false, false><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    if (lim && sat) batch_stage_kernel<R, true, true, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    else if (lim) batch_stage_kernel<R, true, false, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    else if (sat) batch_stage_kernel<R, false, true, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    else batch_stage_kernel<R, false, false, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
+}
+
+template <typename R>
+static void launch_stage_b(const BatchPlan* bp, const BatchBufs& a, int stage, hipStream_t st) {
+    if (bp->kmode == 0) launch_stage_km<R, 0>(bp, a, stage, st);
+    else if (bp->kmode == 1) launch_stage_km<R, 1>(bp, a, stage, st);
+    else launch_stage_km<R, 2>(bp, a, stage, st);
 }
 
 hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st) {

@@ -110,7 +110,7 @@ struct StageLaunch {
     double fac;
 };
 
-template <typename R, bool LIM, bool SAT, int BX, int BY>
+template <typename R, bool LIM, bool SAT, int KM, int BX, int BY>
 __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
     constexpr int PL = (BX + 2) * (BY + 2);
     __shared__ TileLds<R, PL, (BX + 1) * BY, BX*(BY + 1)> L;
@@ -149,16 +149,22 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
     fk.kperp = R(P.kperp);
     fk.satq = R(P.satq);
     fk.tref = R(tref);
-    fk.kmode = P.kmode;
-    run_tile<R, LIM, SAT>(a, fk, tref, L);
+    run_tile<R, LIM, SAT, KM>(a, fk, tref, L);
+}
+
+template <typename R, int KM, int BX, int BY>
+static void launch_km(const StageLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
+    if (lim && sat) stage_kernel<R, true, true, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    else if (lim) stage_kernel<R, true, false, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    else if (sat) stage_kernel<R, false, true, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    else stage_kernel<R, false, false, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
 }
 
 template <typename R, int BX, int BY>
 static hipError_t launch_shape(const StageLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
-    if (lim && sat) stage_kernel<R, true, true, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (lim) stage_kernel<R, true, false, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (sat) stage_kernel<R, false, true, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
-    else stage_kernel<R, false, false, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    if (P.kmode == 0) launch_km<R, 0, BX, BY>(P, nblocks, lim, sat, st);
+    else if (P.kmode == 1) launch_km<R, 1, BX, BY>(P, nblocks, lim, sat, st);
+    else launch_km<R, 2, BX, BY>(P, nblocks, lim, sat, st);
     return hipGetLastError();
 }
 

@@ -19,10 +19,11 @@
 // computes its +x, +y and +z faces, the tile's -x and -y boundary faces are
 // extra jobs, x/y faces are exchanged through (double-buffered) LDS and the
 // +z face is carried in a register to the next plane.  Each thread keeps the
-// three input planes of its own column (and of its halo cell) in registers,
-// so the z-slopes need no LDS and one barrier per plane suffices.  Flux
-// arithmetic runs in R (double, or float on temperatures offset by a
-// reference value); the stage recurrence always runs in double.
+// three input planes of its own column (and of its halo cell), and its own
+// slopes and unit vectors, in registers, so the z-slopes need no LDS, the
+// low side of its faces comes from registers, and one barrier per plane
+// suffices.  Flux arithmetic runs in R (double, or float on temperatures
+// offset by a reference value); the stage recurrence always runs in double.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -54,20 +55,34 @@ __device__ __forceinline__ double r_rcp(double x) {
 __device__ __forceinline__ float r_pow(float x, float y) { return powf(x, y); }
 __device__ __forceinline__ double r_pow(double x, double y) { return pow(x, y); }
 
-// monotonized-central limiter: minmod(2a, 2b, (a+b)/2)
-template <typename R>
-__device__ __forceinline__ R mc(R a, R b) {
-    const R m = fmin(fabs(a + b) * R(0.5), R(2) * fmin(fabs(a), fabs(b)));
-    return (a * b > R(0)) ? copysign(m, a) : R(0);
+// median of three
+__device__ __forceinline__ float med3(float a, float b, float c) { return __builtin_amdgcn_fmed3f(a, b, c); }
+__device__ __forceinline__ double med3(double a, double b, double c) {
+    return fmax(fmin(a, b), fmin(fmax(a, b), c));
 }
 
-// cell slope along one axis from the two one-sided differences: MC-limited,
-// or their mean (so that the mean of two cell slopes is the mean of the four
-// one-sided differences of Appendix B)
+// Monotonized-central limiter, MC(a, b) = minmod(2a, 2b, (a+b)/2).  With
+// minmod(a, b) = med3(a, b, 0) and minmod associative and positively
+// homogeneous, MC(a, b) = minmod(2 minmod(a, b), (a+b)/2)
+// = (1/2) med3(4 med3(a, b, 0), a + b, 0).  mc2 returns 2 MC(a, b).
+template <typename R>
+__device__ __forceinline__ R mc2(R a, R b) {
+    return med3(R(4) * med3(a, b, R(0)), a + b, R(0));
+}
+
+// Cell slope along one axis from the one-sided differences (t0-tm)/h and
+// (tp-t0)/h: MC-limited, or their mean (so that the mean of two cell slopes
+// is the mean of the four one-sided differences of Appendix B).  hih = 1/(2h).
 template <typename R, bool LIM>
-__device__ __forceinline__ R cell_slope(R tm, R t0, R tp, R ih) {
-    const R am = (t0 - tm) * ih, ap = (tp - t0) * ih;
-    return LIM ? mc(am, ap) : R(0.5) * (am + ap);
+__device__ __forceinline__ R cell_slope(R tm, R t0, R tp, R hih) {
+    if (LIM) return hih * mc2(t0 - tm, tp - t0);
+    return hih * (tp - tm);
+}
+
+// transverse gradient at a face from the slopes of its two cells
+template <typename R, bool LIM>
+__device__ __forceinline__ R face_transverse(R sL, R sR) {
+    return R(0.5) * (LIM ? mc2(sL, sR) : sL + sR);
 }
 
 // per-grid constants of the face flux, in the flux precision
@@ -75,34 +90,33 @@ template <typename R>
 struct FaceK {
     R kappa0, kexp, kperp, satq;  // satq = 5 phi rho
     R tref;                       // added back to offset temperatures
-    int kmode;                    // 0: kappa0, 1: kappa0 T^2.5, 2: kappa0 T^kexp
 };
 
 // Normal component of F_c through a face, for cells L (low) and R (high)
 // along the face normal.  s?1, s?2: the cells' slopes along the two
 // transverse axes; b?n/b?1/b?2: the cells' unit vectors (normal, transverse
-// 1, transverse 2 components).
+// 1, transverse 2 components).  KM: conductivity law, 0 kappa0, 1 kappa0
+// T^2.5, 2 kappa0 T^kexp.
 //
 // With c = b_L + b_R the face direction is c/|c| (0 if |c| < 1e-12), so
 // b_n (b.G) = c_n (c.G)/|c|^2, and the magnitude of the classical flux
 // -[k_perp G + (k_par-k_perp) b (b.G)] follows from
 // |F|^2 = k_perp^2 |G|^2 + (k_par^2 - k_perp^2) (b.G)^2.
 // kappa_par = kappa0 T^2.5 is evaluated as kappa0 T^3 / sqrt(T) and the
-// saturated flux 5 phi rho T^1.5 as satq T^2 / sqrt(T) (one reciprocal root).
-template <typename R, bool LIM, bool SAT>
+// saturated flux 5 phi rho T^1.5 as satq T^2 / sqrt(T) (one reciprocal root;
+// T is clipped at 1e-30 instead of 0 so that the root stays finite, which
+// changes kappa and q by less than 1e-75).
+template <typename R, bool LIM, bool SAT, int KM>
 __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R sR2,
                                        R bLn, R bL1, R bL2, R bRn, R bR1, R bR2,
                                        const FaceK<R>& k) {
     const R Gn = (TR - TL) * ihn;
-    const R G1 = LIM ? mc(sL1, sR1) : R(0.5) * (sL1 + sR1);
-    const R G2 = LIM ? mc(sL2, sR2) : R(0.5) * (sL2 + sR2);
-    R Tf = R(0.5) * (TL + TR) + k.tref;
-    Tf = Tf > R(0) ? Tf : R(0);
-    const bool need_rs = SAT || k.kmode == 1;
-    const R rs = (need_rs && Tf > R(0)) ? r_rsqrt(Tf) : R(0);
+    const R G1 = face_transverse<R, LIM>(sL1, sR1);
+    const R G2 = face_transverse<R, LIM>(sL2, sR2);
+    const R Tf = fmax(R(0.5) * (TL + TR) + k.tref, R(1e-30));
+    const R rs = (SAT || KM == 1) ? r_rsqrt(Tf) : R(0);
     const R T2 = Tf * Tf;
-    const R kpar = k.kmode == 0 ? k.kappa0
-                 : (k.kmode == 1 ? k.kappa0 * (T2 * Tf * rs) : k.kappa0 * r_pow(Tf, k.kexp));
+    const R kpar = KM == 0 ? k.kappa0 : (KM == 1 ? k.kappa0 * (T2 * Tf * rs) : k.kappa0 * r_pow(Tf, k.kexp));
     const R kperp = k.kperp * kpar;
     const R cn = bLn + bRn, c1 = bL1 + bR1, c2 = bL2 + bR2;
     const R cc = cn * cn + c1 * c1 + c2 * c2;
@@ -112,10 +126,11 @@ __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R
     R Fn = -(kperp * Gn + dk * (cn * w));
     if (SAT) {
         const R GG = Gn * Gn + G1 * G1 + G2 * G2;
-        R F2 = kperp * kperp * GG + dk * (kpar + kperp) * (cG * w);
-        const R Fm = r_sqrt(F2 > R(0) ? F2 : R(0));
+        const R F2 = kperp * kperp * GG + dk * (kpar + kperp) * (cG * w);
+        const R Fm = r_sqrt(fmax(F2, R(0)));
         const R q = k.satq * (T2 * rs);
-        Fn = q > R(0) ? Fn * (q * r_rcp(q + Fm)) : R(0);
+        const R qF = q + Fm;
+        Fn = qF > R(0) ? Fn * (q * r_rcp(qF)) : R(0);
     }
     return Fn;
 }
@@ -157,7 +172,7 @@ __device__ __forceinline__ R to_r(double v, double tref) {
     return R(v - tref);
 }
 
-template <typename R, bool LIM, bool SAT, int PLMAX, int FXMAX, int FYMAX>
+template <typename R, bool LIM, bool SAT, int KM, int PLMAX, int FXMAX, int FYMAX>
 __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, double tref,
                                          TileLds<R, PLMAX, FXMAX, FYMAX>& L) {
     const int tid = threadIdx.x;
@@ -169,6 +184,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     const R* b1 = b0 + N;
     const R* b2 = b1 + N;
     const R ih0 = R(a.ih0), ih1 = R(a.ih1), ih2 = R(a.ih2);
+    const R hih0 = R(0.5 * a.ih0), hih1 = R(0.5 * a.ih1), hih2 = R(0.5 * a.ih2);
     const bool do_y = a.ndim >= 2, do_z = a.ndim >= 3;
 
     // own cell of this thread
@@ -212,7 +228,6 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     const int z0 = a.z0, z1 = a.z1;
     // wrapped plane index of k + 3 (prefetched temperature plane), incremented per plane
     int pz3 = wrap(z0 + 1, n2);
-    auto inc = [&](int p) { return p + 1 == n2 ? 0 : p + 1; };
 
     // pipeline registers
     double pTo = 0.0;                         // prefetched T(k+2), own cell (FP64)
@@ -224,8 +239,13 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     R hq0 = 0, hq1 = 0, hq2 = 0;              // halo cell input, planes k, k+1, k+2
     R ob00 = 0, ob01 = 0, ob02 = 0;           // own b, plane k
     R ob10 = 0, ob11 = 0, ob12 = 0;           // own b, plane k+1
-    R os00 = 0, os01 = 0, os10 = 0, os11 = 0; // own x/y slopes, planes k and k+1
+    R os00 = 0, os01 = 0, os02 = 0;           // own slopes, plane k
+    R os10 = 0, os11 = 0, os12 = 0;           // own slopes, plane k+1
     R fzp = 0;                                // +z face flux of plane k-1
+    // pointwise stage inputs Y_{j-2}, Y0, tau M(Y0) of plane k (cur) and k+1
+    // (nxt): loaded one plane ahead so that no wait covers this plane's loads
+    double ym2 = 0.0, y0v = 0.0, my0 = 0.0, nym2 = 0.0, ny0v = 0.0, nmy0 = 0.0;
+    const bool pw = own && a.kind == 2;
 
     // ring slots: T(k) c0, T(k+1) c1, T(k+2) c2; slopes/b of plane k in dc, of k+1 in dn
     int c0 = 0, c1 = 1, c2 = 2, dc = 1, dn = 0, fb = 0;
@@ -281,34 +301,38 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
             }
             if (hjob) pTh = to_r<R>(pt[hxy], tref);
             if (djob) { pbd0 = b0[pb + hxy]; pbd1 = b1[pb + hxy]; pbd2 = b2[pb + hxy]; }
-            pz3 = inc(pz3);
+            pz3 = pz3 + 1 == n2 ? 0 : pz3 + 1;
         }
-        double ym2 = 0.0, y0v = 0.0, my0 = 0.0;
-        if (k >= z0 && own && a.kind == 2) {
-            const size_t o = (size_t)k * plane + oxy;
-            ym2 = a.Ym2[o];
-            y0v = a.Y0[o];
-            my0 = (double)((const R*)a.MY0in)[o];
+        ym2 = nym2;
+        y0v = ny0v;
+        my0 = nmy0;
+        if (pw && k + 1 >= z0 && k + 1 < z1) {
+            const size_t o = (size_t)(k + 1) * plane + oxy;
+            nym2 = a.Ym2[o];
+            ny0v = a.Y0[o];
+            nmy0 = (double)((const R*)a.MY0in)[o];
         }
 
         // ---- B: slopes of plane k+1.  In-plane neighbours of T(k+1) come from
         // the ring (written one plane earlier); z neighbours from registers.
         if (own) {
             const R* T1 = L.T[c1];
-            const R s0 = cell_slope<R, LIM>(T1[oslot - 1], oq1, T1[oslot + 1], ih0);
-            const R s1 = cell_slope<R, LIM>(T1[oslot - px], oq1, T1[oslot + px], ih1);
-            const R s2 = cell_slope<R, LIM>(oq0, oq1, oq2, ih2);
+            const R s0 = cell_slope<R, LIM>(T1[oslot - 1], oq1, T1[oslot + 1], hih0);
+            const R s1 = cell_slope<R, LIM>(T1[oslot - px], oq1, T1[oslot + px], hih1);
+            const R s2 = cell_slope<R, LIM>(oq0, oq1, oq2, hih2);
             L.S[dn][0][oslot] = s0; L.S[dn][1][oslot] = s1; L.S[dn][2][oslot] = s2;
-            os00 = os10; os01 = os11; os10 = s0; os11 = s1;
+            os00 = os10; os01 = os11; os02 = os12;
+            os10 = s0; os11 = s1; os12 = s2;
         }
         if (djob) {
             const R* T1 = L.T[c1];
-            if (dxh) L.S[dn][1][hslot] = cell_slope<R, LIM>(T1[hslot - px], hq1, T1[hslot + px], ih1);
-            else     L.S[dn][0][hslot] = cell_slope<R, LIM>(T1[hslot - 1], hq1, T1[hslot + 1], ih0);
-            L.S[dn][2][hslot] = cell_slope<R, LIM>(hq0, hq1, hq2, ih2);
+            if (dxh) L.S[dn][1][hslot] = cell_slope<R, LIM>(T1[hslot - px], hq1, T1[hslot + px], hih1);
+            else     L.S[dn][0][hslot] = cell_slope<R, LIM>(T1[hslot - 1], hq1, T1[hslot + 1], hih0);
+            L.S[dn][2][hslot] = cell_slope<R, LIM>(hq0, hq1, hq2, hih2);
         }
 
-        // ---- C: faces of plane k (inputs written in earlier planes)
+        // ---- C: faces of plane k (inputs written in earlier planes; the low
+        // side of the own faces from registers)
         R fzn = 0;
         if (k >= z0) {
             const R* Tk = L.T[c0];
@@ -318,28 +342,28 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
             R* FY = L.FY[fb];
             if (own) {
                 const int r = oslot + 1;
-                FX[ty * (bx + 1) + tx + 1] = face_flux<R, LIM, SAT>(
-                    oq0, Tk[r], ih0, S[1][oslot], S[1][r], S[2][oslot], S[2][r],
-                    Bv[0][oslot], Bv[1][oslot], Bv[2][oslot], Bv[0][r], Bv[1][r], Bv[2][r], fk);
+                FX[ty * (bx + 1) + tx + 1] = face_flux<R, LIM, SAT, KM>(
+                    oq0, Tk[r], ih0, os01, S[1][r], os02, S[2][r],
+                    ob00, ob01, ob02, Bv[0][r], Bv[1][r], Bv[2][r], fk);
                 if (do_y) {
                     const int u = oslot + px;
-                    FY[(ty + 1) * bx + tx] = face_flux<R, LIM, SAT>(
-                        oq0, Tk[u], ih1, S[0][oslot], S[0][u], S[2][oslot], S[2][u],
-                        Bv[1][oslot], Bv[0][oslot], Bv[2][oslot], Bv[1][u], Bv[0][u], Bv[2][u], fk);
+                    FY[(ty + 1) * bx + tx] = face_flux<R, LIM, SAT, KM>(
+                        oq0, Tk[u], ih1, os00, S[0][u], os02, S[2][u],
+                        ob01, ob00, ob02, Bv[1][u], Bv[0][u], Bv[2][u], fk);
                 }
             }
             if (fjob) {
                 // direction-generic gather so that the wave runs one face evaluation
                 const int t1 = fdir == 0 ? 1 : 0;
-                const R f = face_flux<R, LIM, SAT>(
+                const R f = face_flux<R, LIM, SAT, KM>(
                     Tk[fL], Tk[fR], fdir == 0 ? ih0 : ih1, S[t1][fL], S[t1][fR], S[2][fL], S[2][fR],
                     Bv[fdir][fL], Bv[t1][fL], Bv[2][fL], Bv[fdir][fR], Bv[t1][fR], Bv[2][fR], fk);
                 if (fdir == 0) FX[fidx] = f; else FY[fidx] = f;
             }
         }
         if (do_z && own && k >= z0 - 1) {
-            fzn = face_flux<R, LIM, SAT>(oq0, oq1, ih2, os00, os10, os01, os11,
-                                         ob02, ob00, ob01, ob12, ob10, ob11, fk);
+            fzn = face_flux<R, LIM, SAT, KM>(oq0, oq1, ih2, os00, os10, os01, os11,
+                                             ob02, ob00, ob01, ob12, ob10, ob11, fk);
         }
         __syncthreads();
 

@@ -24,7 +24,7 @@ EXPORTS = [
     "rkl_plan", "rkl_destroy", "rkl_grid_offset", "rkl_flux_div", "rkl_dt_par",
     "rkl_superstep", "rkl_superstep_batched", "rkl_graph_capture", "rkl_graph_launch",
     "rkl_query", "rkl_variant_count", "rkl_variant_info", "rkl_set_variant", "rkl_last_error",
-    "rkl_profile", "rkl_profile_read",
+    "rkl_profile", "rkl_profile_read", "rkl_autotune",
 ]
 
 
@@ -93,6 +93,7 @@ def load(build_if_missing: bool = True):
         "rkl_last_error": (ctypes.c_char_p, []),
         "rkl_profile": (i32, [vp, i32]),
         "rkl_profile_read": (i32, [vp, P(dbl), P(i64), P(i64)]),
+        "rkl_autotune": (i32, [vp, i32, vp, vp, dbl, i32, P(i32), P(dbl), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -174,6 +175,13 @@ def rkl_set_variant(plan, v):
 
 def rkl_last_error():
     return load().rkl_last_error().decode()
+
+
+def rkl_autotune(plan, grid, T_ptr, b_ptr, dt_hyp, reps, stream):
+    v, ms = ctypes.c_int32(), ctypes.c_double()
+    _check(load().rkl_autotune(plan, grid, T_ptr, b_ptr, float(dt_hyp), int(reps), ctypes.byref(v),
+                               ctypes.byref(ms), stream))
+    return v.value, ms.value
 
 
 def rkl_profile(plan, enable):
@@ -267,6 +275,12 @@ class Plan:
 
     def set_variant(self, v):
         rkl_set_variant(self.handle, v)
+
+    def autotune(self, T, b, dt_hyp, reps=2, grid=0, cache=None):
+        """Pick the fastest stencil variant for this grid (see tune.py for the
+        JSON cache); returns (variant, ms per super-step, from_cache)."""
+        from . import tune
+        return tune.autotune(self, T, b, dt_hyp, reps=reps, grid=grid, cache=cache)
 
     # batched: packed tensors
     def offsets(self):

@@ -1,0 +1,74 @@
+"""Autotuner front end: picks the stencil kernel variant (tile shape and
+z-chunk length) for a grid by timing every variant on the caller's own
+fields (``rkl_autotune`` in librkl), and remembers the choice in a JSON cache
+keyed by everything that changes the kernel's cost: device name, grid shape,
+flux precision, limiter, saturation and conductivity law.
+
+Cache file: $RKL_TUNE_CACHE, else ~/.cache/rkl/tune.json.  Writes are atomic
+(temp file + rename); a corrupt or unreadable cache is ignored.
+"""
+from __future__ import annotations
+
+import json
+import os
+import tempfile
+
+from . import rkl
+
+
+def cache_path(path=None):
+    if path:
+        return path
+    env = os.environ.get("RKL_TUNE_CACHE")
+    if env:
+        return env
+    return os.path.join(os.path.expanduser("~"), ".cache", "rkl", "tune.json")
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path, d):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=os.path.dirname(path) or ".", prefix=".tune")
+    with os.fdopen(fd, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def key(plan, grid):
+    import torch
+    d = plan.descs[grid]
+    kind = "const" if d.kappa_exp == 0.0 else ("spitzer" if d.kappa_exp == 2.5 else "power")
+    return "|".join(str(x) for x in (
+        torch.cuda.get_device_name(0), tuple(d.n), d.ndim,
+        "mixed" if plan.precision == rkl.RKL_MIXED else "fp64",
+        "mc" if d.limiter else "mean", "sat" if d.saturation else "nosat", kind,
+        rkl.rkl_variant_count()))
+
+
+def autotune(plan, T, b, dt_hyp, reps=2, grid=0, cache=None):
+    """Set plan's variant to the fastest one; returns (variant, ms, cached)."""
+    import torch
+    path = cache_path(cache)
+    k = key(plan, grid)
+    d = _load(path)
+    if k in d and 0 <= d[k].get("variant", -1) < rkl.rkl_variant_count():
+        plan.set_variant(d[k]["variant"])
+        return d[k]["variant"], d[k].get("ms"), True
+    tp, bp = plan._tb(grid, T, b)
+    v, ms = rkl.rkl_autotune(plan.handle, grid, tp, bp, dt_hyp, reps,
+                             rkl.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    d = _load(path)
+    d[k] = {"variant": v, "ms": ms, "tile": list(rkl.rkl_variant_info(v))}
+    try:
+        _save(path, d)
+    except OSError:
+        pass
+    return v, ms, False
