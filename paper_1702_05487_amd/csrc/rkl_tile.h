@@ -226,14 +226,16 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     }
 
     const int z0 = a.z0, z1 = a.z1;
-    // wrapped plane index of k + 3 (prefetched temperature plane), incremented per plane
-    int pz3 = wrap(z0 + 1, n2);
+    // wrapped index of plane k + 4, the temperature plane prefetched at plane k
+    int pz4 = wrap(z0 + 2, n2);
 
-    // pipeline registers
-    double pTo = 0.0;                         // prefetched T(k+2), own cell (FP64)
-    R pTh = 0;                                // prefetched T(k+2), halo cell
-    R pbo0 = 0, pbo1 = 0, pbo2 = 0;           // prefetched b(k+1), own
-    R pbd0 = 0, pbd1 = 0, pbd2 = 0;           // prefetched b(k+1), halo
+    // Prefetch pipeline, two planes deep: set 0 is stored into LDS at this
+    // plane's step A, set 1 at the next plane's.  Values stay in their loaded
+    // type until they are used, so that no conversion forces an early wait.
+    double pTo0 = 0.0, pTo1 = 0.0;            // T(k+2), T(k+3): own cell
+    double pTh0 = 0.0, pTh1 = 0.0;            // T(k+2), T(k+3): halo cell
+    R pbo00 = 0, pbo01 = 0, pbo02 = 0, pbo10 = 0, pbo11 = 0, pbo12 = 0;   // b(k+1), b(k+2): own
+    R pbd00 = 0, pbd01 = 0, pbd02 = 0, pbd10 = 0, pbd11 = 0, pbd12 = 0;   // b(k+1), b(k+2): halo
     double yq0 = 0.0, yq1 = 0.0, yq2 = 0.0;   // own FP64 input, planes k, k+1, k+2
     R oq0 = 0, oq1 = 0, oq2 = 0;              // same in flux precision
     R hq0 = 0, hq1 = 0, hq2 = 0;              // halo cell input, planes k, k+1, k+2
@@ -242,9 +244,12 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     R os00 = 0, os01 = 0, os02 = 0;           // own slopes, plane k
     R os10 = 0, os11 = 0, os12 = 0;           // own slopes, plane k+1
     R fzp = 0;                                // +z face flux of plane k-1
-    // pointwise stage inputs Y_{j-2}, Y0, tau M(Y0) of plane k (cur) and k+1
-    // (nxt): loaded one plane ahead so that no wait covers this plane's loads
-    double ym2 = 0.0, y0v = 0.0, my0 = 0.0, nym2 = 0.0, ny0v = 0.0, nmy0 = 0.0;
+    // pointwise stage inputs Y_{j-2}, Y0, tau M(Y0): plane k (cur), k+1 (q1),
+    // k+2 (q2), loaded two planes ahead
+    double ym2 = 0.0, y0v = 0.0;
+    R my0 = 0;
+    double q1ym2 = 0.0, q1y0 = 0.0, q2ym2 = 0.0, q2y0 = 0.0;
+    R q1my0 = 0, q2my0 = 0;
     const bool pw = own && a.kind == 2;
 
     // ring slots: T(k) c0, T(k+1) c1, T(k+2) c2; slopes/b of plane k in dc, of k+1 in dn
@@ -253,64 +258,77 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
         const double* p0 = a.Yin + (size_t)wrap(z0 - 2, n2) * plane;
         const double* p1 = a.Yin + (size_t)wrap(z0 - 1, n2) * plane;
         const double* p2 = a.Yin + (size_t)wrap(z0, n2) * plane;
-        const size_t pb = (size_t)wrap(z0 - 1, n2) * plane;
+        const double* p3 = a.Yin + (size_t)wrap(z0 + 1, n2) * plane;
+        const size_t pb0 = (size_t)wrap(z0 - 1, n2) * plane;
+        const size_t pb1 = (size_t)wrap(z0, n2) * plane;
         if (own) {
             yq1 = p0[oxy];
             yq2 = p1[oxy];
+            pTo0 = p2[oxy];
+            pTo1 = p3[oxy];
+            pbo00 = b0[pb0 + oxy]; pbo01 = b1[pb0 + oxy]; pbo02 = b2[pb0 + oxy];
+            pbo10 = b0[pb1 + oxy]; pbo11 = b1[pb1 + oxy]; pbo12 = b2[pb1 + oxy];
+        }
+        if (hjob) {
+            const double h1 = p0[hxy], h2 = p1[hxy];
+            pTh0 = p2[hxy];
+            pTh1 = p3[hxy];
+            hq1 = to_r<R>(h1, tref);
+            hq2 = to_r<R>(h2, tref);
+            L.T[0][hslot] = hq1;
+            L.T[1][hslot] = hq2;
+        }
+        if (djob) {
+            pbd00 = b0[pb0 + hxy]; pbd01 = b1[pb0 + hxy]; pbd02 = b2[pb0 + hxy];
+            pbd10 = b0[pb1 + hxy]; pbd11 = b1[pb1 + hxy]; pbd12 = b2[pb1 + hxy];
+        }
+        if (own) {
             oq1 = to_r<R>(yq1, tref);
             oq2 = to_r<R>(yq2, tref);
             L.T[0][oslot] = oq1;
             L.T[1][oslot] = oq2;
-            pTo = p2[oxy];
-            pbo0 = b0[pb + oxy]; pbo1 = b1[pb + oxy]; pbo2 = b2[pb + oxy];
         }
-        if (hjob) {
-            hq1 = to_r<R>(p0[hxy], tref);
-            hq2 = to_r<R>(p1[hxy], tref);
-            L.T[0][hslot] = hq1;
-            L.T[1][hslot] = hq2;
-            pTh = to_r<R>(p2[hxy], tref);
-        }
-        if (djob) { pbd0 = b0[pb + hxy]; pbd1 = b1[pb + hxy]; pbd2 = b2[pb + hxy]; }
     }
     __syncthreads();
 
     for (int k = z0 - 2; k < z1; ++k) {
         // ---- A: T(k+2) into the ring and the register queues, b(k+1) into the b ring
         if (own) {
-            yq0 = yq1; yq1 = yq2; yq2 = pTo;
-            oq0 = oq1; oq1 = oq2; oq2 = to_r<R>(pTo, tref);
+            yq0 = yq1; yq1 = yq2; yq2 = pTo0;
+            oq0 = oq1; oq1 = oq2; oq2 = to_r<R>(pTo0, tref);
             L.T[c2][oslot] = oq2;
-            L.B[dn][0][oslot] = pbo0; L.B[dn][1][oslot] = pbo1; L.B[dn][2][oslot] = pbo2;
+            L.B[dn][0][oslot] = pbo00; L.B[dn][1][oslot] = pbo01; L.B[dn][2][oslot] = pbo02;
             ob00 = ob10; ob01 = ob11; ob02 = ob12;
-            ob10 = pbo0; ob11 = pbo1; ob12 = pbo2;
+            ob10 = pbo00; ob11 = pbo01; ob12 = pbo02;
         }
         if (hjob) {
-            hq0 = hq1; hq1 = hq2; hq2 = pTh;
+            hq0 = hq1; hq1 = hq2; hq2 = to_r<R>(pTh0, tref);
             L.T[c2][hslot] = hq2;
         }
-        if (djob) { L.B[dn][0][hslot] = pbd0; L.B[dn][1][hslot] = pbd1; L.B[dn][2][hslot] = pbd2; }
-        // prefetch the next plane: T(k+3) and b(k+2)
-        if (k + 1 < z1) {
-            const double* pt = a.Yin + (size_t)pz3 * plane;
-            const int pbz = pz3 == 0 ? n2 - 1 : pz3 - 1;
+        if (djob) { L.B[dn][0][hslot] = pbd00; L.B[dn][1][hslot] = pbd01; L.B[dn][2][hslot] = pbd02; }
+        pTo0 = pTo1; pTh0 = pTh1;
+        pbo00 = pbo10; pbo01 = pbo11; pbo02 = pbo12;
+        pbd00 = pbd10; pbd01 = pbd11; pbd02 = pbd12;
+        // prefetch two planes ahead: T(k+4) and b(k+3), used at plane k+2
+        if (k + 2 < z1) {
+            const double* pt = a.Yin + (size_t)pz4 * plane;
+            const int pbz = pz4 == 0 ? n2 - 1 : pz4 - 1;
             const size_t pb = (size_t)pbz * plane;
             if (own) {
-                pTo = pt[oxy];
-                pbo0 = b0[pb + oxy]; pbo1 = b1[pb + oxy]; pbo2 = b2[pb + oxy];
+                pTo1 = pt[oxy];
+                pbo10 = b0[pb + oxy]; pbo11 = b1[pb + oxy]; pbo12 = b2[pb + oxy];
             }
-            if (hjob) pTh = to_r<R>(pt[hxy], tref);
-            if (djob) { pbd0 = b0[pb + hxy]; pbd1 = b1[pb + hxy]; pbd2 = b2[pb + hxy]; }
-            pz3 = pz3 + 1 == n2 ? 0 : pz3 + 1;
+            if (hjob) pTh1 = pt[hxy];
+            if (djob) { pbd10 = b0[pb + hxy]; pbd11 = b1[pb + hxy]; pbd12 = b2[pb + hxy]; }
+            pz4 = pz4 + 1 == n2 ? 0 : pz4 + 1;
         }
-        ym2 = nym2;
-        y0v = ny0v;
-        my0 = nmy0;
-        if (pw && k + 1 >= z0 && k + 1 < z1) {
-            const size_t o = (size_t)(k + 1) * plane + oxy;
-            nym2 = a.Ym2[o];
-            ny0v = a.Y0[o];
-            nmy0 = (double)((const R*)a.MY0in)[o];
+        ym2 = q1ym2; y0v = q1y0; my0 = q1my0;
+        q1ym2 = q2ym2; q1y0 = q2y0; q1my0 = q2my0;
+        if (pw && k + 2 >= z0 && k + 2 < z1) {
+            const size_t o = (size_t)(k + 2) * plane + oxy;
+            q2ym2 = a.Ym2[o];
+            q2y0 = a.Y0[o];
+            q2my0 = ((const R*)a.MY0in)[o];
         }
 
         // ---- B: slopes of plane k+1.  In-plane neighbours of T(k+1) come from
@@ -384,7 +402,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
                 ((R*)a.MY0out)[o] = m;
                 a.Yout[o] = yq0 + a.mut * (double)m;
             } else {
-                a.Yout[o] = a.mu * yq0 + a.nu * ym2 + a.omn * y0v + a.mut * tl + a.gt * my0;
+                a.Yout[o] = a.mu * yq0 + a.nu * ym2 + a.omn * y0v + a.mut * tl + a.gt * (double)my0;
             }
         }
         fzp = fzn;
