@@ -217,12 +217,18 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
         hslot = (hj + 1) * px + hi + 1;
         hxy = wrap(a.y0 + hj, n1) * n0 + wrap(a.x0 + hi, n0);
     }
-    // extra face: the tile's -x face of row j (tid < by) or -y face of column i
-    const bool fjob = tid < by + (do_y ? bx : 0);
+    // extra face: the tile's -x face of row j (f < by) or -y face of column i.
+    // These jobs go to the last wave(s) of the workgroup while the halo jobs
+    // sit in the first ones, so that no wave carries both (wave w of every
+    // workgroup runs on the same SIMD).
+    const int nf = by + (do_y ? bx : 0);
+    const int fbase = max(0, ((int)blockDim.x - nf) / 64 * 64);
+    const int fid = tid - fbase;
+    const bool fjob = fid >= 0 && fid < nf;
     int fdir = 0, fL = 0, fR = 0, fidx = 0;
     if (fjob) {
-        if (tid < by) { fdir = 0; fL = (tid + 1) * px; fR = fL + 1; fidx = tid * (bx + 1); }
-        else { const int i = tid - by; fdir = 1; fL = i + 1; fR = px + i + 1; fidx = i; }
+        if (fid < by) { fdir = 0; fL = (fid + 1) * px; fR = fL + 1; fidx = fid * (bx + 1); }
+        else { const int i = fid - by; fdir = 1; fL = i + 1; fR = px + i + 1; fidx = i; }
     }
 
     const int z0 = a.z0, z1 = a.z1;
