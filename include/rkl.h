@@ -82,7 +82,7 @@ typedef struct {
 
 typedef struct {
     int32_t precision;    /* RKL_FP64 or RKL_MIXED */
-    int32_t variant;      /* stencil kernel variant (tile shape); -1 = library default */
+    int32_t variant;      /* stencil kernel variant (see rkl_variant_info); -1 = library default */
     int32_t smax;         /* largest stage count accepted (coefficient table size); 0 = 1024
                              for one grid, 64 for several (a batched super-step issues
                              one stage launch per stage up to smax) */
@@ -172,26 +172,39 @@ rkl_status rkl_graph_launch(rkl_plan_t plan, void *stream);
 rkl_status rkl_query(rkl_plan_t plan, int32_t grid, int32_t *last_s, double *last_dt_par,
                      uint32_t *flags);
 
-/* Stencil kernel variants: rkl_variant_count() of them, each a tile shape
- * (rkl_variant_info fills tile_x, tile_y, tile_z cells).  rkl_set_variant
- * selects one for a plan (used by the autotuner). */
+/*
+ * Stencil kernel variants: rkl_variant_count() of them.  rkl_variant_info
+ * fills the workgroup tile (tile_x x tile_y cells, a z-chunk of tile_z
+ * planes) and the stages per launch `fuse` (any pointer may be NULL):
+ *   fuse 1: one RKL2 stage per launch, output tile = tile_x x tile_y;
+ *   fuse 2: stages j and j+1 in one launch (temporal fusion of Appendix A's
+ *           recurrence; 2 <= j, j+1 < s, the last stage always runs alone),
+ *           output tile (tile_x-2) x (tile_y-2): the tile's border ring is
+ *           recomputed by the neighbouring tiles.  RKL_MIXED plans of 3-D
+ *           grids only; selecting one allocates two more FP64 stage buffers.
+ * rkl_set_variant selects a variant for a plan (RKL_EINVAL if the plan
+ * cannot use it, RKL_ENOMEM); the autotuner calls it.
+ */
 int32_t rkl_variant_count(void);
-rkl_status rkl_variant_info(int32_t variant, int32_t *tile_x, int32_t *tile_y, int32_t *tile_z);
+rkl_status rkl_variant_info(int32_t variant, int32_t *tile_x, int32_t *tile_y, int32_t *tile_z,
+                            int32_t *fuse);
 rkl_status rkl_set_variant(rkl_plan_t plan, int32_t variant);
 
 /*
  * Kernel timing for benchmarks.  rkl_profile(plan, 1) starts recording, with
- * HIP events on the caller's stream, the span of the stage-j >= 2 stencil
- * kernels of every following rkl_superstep (the s-1 back-to-back launches of
- * the dominant kernel); rkl_profile(plan, 0) stops and discards.
- * rkl_profile_read synchronises, and returns the summed span in ms, the
- * number of kernel launches and of cell-stage updates it covers.
+ * a pair of HIP events on the caller's stream around each stencil launch of
+ * stages j >= 2 of every following rkl_superstep (the dominant kernels);
+ * rkl_profile(plan, 0) stops and discards.  rkl_profile_read synchronises
+ * and returns, over the launches with `fuse` stages each (1 or 2), the summed
+ * duration in ms, the number of launches and of cell-stage updates.
  */
 rkl_status rkl_profile(rkl_plan_t plan, int32_t enable);
-rkl_status rkl_profile_read(rkl_plan_t plan, double *ms, int64_t *launches, int64_t *cell_stages);
+rkl_status rkl_profile_read(rkl_plan_t plan, int32_t fuse, double *ms, int64_t *launches,
+                            int64_t *cell_stages);
 
 /*
- * rkl_autotune: time every stencil variant (tile shape, z-chunk) on `grid`
+ * rkl_autotune: time every stencil variant the plan can use (tile shape,
+ * z-chunk, stages per launch) on `grid`
  * with the caller's fields -- `reps` super-steps of dt_hyp each, on a
  * plan-owned scratch copy of T (T itself is not modified) -- select the
  * fastest for the plan and return its index and average super-step time.

@@ -40,6 +40,8 @@ struct rkl_plan_s {
     int64_t total = 0;
     double* Ya = nullptr;       // stage buffers (FP64), packed
     double* Yb = nullptr;
+    double* Yc = nullptr;       // two more, allocated once a two-stage variant is selected
+    double* Yd = nullptr;
     void* MY0 = nullptr;        // tau M(Y0), FP64 or FP32, packed
     double* coef = nullptr;     // RKL2 table, device
     GridState* state = nullptr; // ngrids entries, device
@@ -49,16 +51,23 @@ struct rkl_plan_s {
     BatchPlan* batch = nullptr; // batched launch data (rkl_batch.hip)
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    // kernel timing (rkl_profile)
+    // kernel timing (rkl_profile): one event pair per stencil launch of
+    // stage j >= 2, tagged with its stages per launch and cell-stages
+    struct ProfRec {
+        hipEvent_t a, b;
+        int fuse;
+        int64_t cells;
+    };
     bool prof = false;
-    std::vector<hipEvent_t> ev;   // start/stop pairs
-    int64_t prof_launches = 0, prof_cells = 0;
+    std::vector<ProfRec> prof_recs;
 };
 
 static void prof_clear(rkl_plan_s* p) {
-    for (hipEvent_t e : p->ev) hipEventDestroy(e);
-    p->ev.clear();
-    p->prof_launches = p->prof_cells = 0;
+    for (auto& r : p->prof_recs) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    p->prof_recs.clear();
 }
 
 // ---------------------------------------------------------------------------
@@ -146,6 +155,8 @@ static void free_plan(rkl_plan_s* p) {
     batch_free(p->batch);
     hipFree(p->Ya);
     hipFree(p->Yb);
+    hipFree(p->Yc);
+    hipFree(p->Yd);
     hipFree(p->MY0);
     hipFree(p->coef);
     hipFree(p->state);
@@ -161,12 +172,40 @@ const char* rkl_last_error(void) { return g_err.c_str(); }
 
 int32_t rkl_variant_count(void) { return variant_count(); }
 
-rkl_status rkl_variant_info(int32_t v, int32_t* tx, int32_t* ty, int32_t* tz) {
+rkl_status rkl_variant_info(int32_t v, int32_t* tx, int32_t* ty, int32_t* tz, int32_t* fuse) {
     if (v < 0 || v >= variant_count()) return fail(RKL_EINVAL, "variant out of range");
     const Variant x = variant_get(v);
     if (tx) *tx = x.bx;
     if (ty) *ty = x.by;
     if (tz) *tz = x.bz;
+    if (fuse) *fuse = x.fuse;
+    return RKL_OK;
+}
+
+// A two-stage variant needs RKL_MIXED and 3-D grids, and two more stage
+// buffers (tiles overlap, so its outputs may not overwrite its inputs).
+static bool fused_ok(const rkl_plan_s* p) {
+    if (p->precision != RKL_MIXED) return false;
+    for (const auto& d : p->desc)
+        if (d.ndim != 3) return false;
+    return true;
+}
+
+static rkl_status select_variant(rkl_plan_s* p, int v) {
+    const Variant x = variant_get(v);
+    if (x.fuse == 2) {
+        if (!fused_ok(p)) return fail(RKL_EINVAL, "two-stage variants need an RKL_MIXED plan of 3-D grids");
+        if (!p->Yc) {
+            if (hipMalloc(&p->Yc, sizeof(double) * p->total) != hipSuccess ||
+                hipMalloc(&p->Yd, sizeof(double) * p->total) != hipSuccess) {
+                hipGetLastError();
+                hipFree(p->Yc);
+                p->Yc = nullptr;
+                return fail(RKL_ENOMEM, "stage buffer allocation failed");
+            }
+        }
+    }
+    p->variant = v;
     return RKL_OK;
 }
 
@@ -185,7 +224,7 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
     rkl_plan_s* p = new rkl_plan_s();
     p->ngrids = ngrids;
     p->precision = o.precision;
-    p->variant = o.variant < 0 ? 0 : o.variant;
+    p->variant = 0;
     p->smax = o.smax;
     p->off.push_back(0);
     for (int g = 0; g < ngrids; ++g) {
@@ -226,6 +265,14 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
         rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, &p->batch, why);
         if (st != RKL_OK) { free_plan(p); return fail(st, why); }
     }
+    if (o.variant > 0) {
+        rkl_status st = select_variant(p, o.variant);
+        if (st != RKL_OK) {
+            const std::string why = g_err;
+            free_plan(p);
+            return fail(st, why);
+        }
+    }
     *out = p;
     return RKL_OK;
 }
@@ -245,8 +292,7 @@ int64_t rkl_grid_offset(rkl_plan_t p, int32_t g) {
 rkl_status rkl_set_variant(rkl_plan_t p, int32_t v) {
     if (!p) return fail(RKL_EINVAL, "plan is NULL");
     if (v < 0 || v >= variant_count()) return fail(RKL_EINVAL, "variant out of range");
-    p->variant = v;
-    return RKL_OK;
+    return select_variant(p, v);
 }
 
 static rkl_status check_grid(rkl_plan_t p, int32_t g) {
@@ -274,7 +320,7 @@ rkl_status rkl_flux_div(rkl_plan_t p, int32_t g, const double* T, const void* b,
     hipStream_t s = (hipStream_t)stream;
     st = reduce_and_finalize(p, g, T, 0.0, 1, nullptr, s);
     if (st != RKL_OK) return st;
-    HIPCHECK(launch_stage(p->precision, p->variant, p->gc[g], 0, 0, T, nullptr, nullptr, nullptr, nullptr,
+    HIPCHECK(launch_stage(p->precision, variant_get(p->variant), p->gc[g], 0, 0, T, nullptr, nullptr, nullptr, nullptr,
                           out, b, p->state + g, p->coef, s),
              "flux_div launch");
     return RKL_OK;
@@ -311,35 +357,56 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
         return fail(RKL_ESTAGES, "stage count " + std::to_string(S) + " outside [2, smax=" + std::to_string(p->smax) + "]");
 
     const GridConst& gc = p->gc[g];
-    double* A = p->Ya + p->off[g];
-    double* B = p->Yb + p->off[g];
+    const Variant v = variant_get(p->variant);
+    const int64_t n = p->off[g + 1] - p->off[g];
+    double* bufs[4] = {p->Ya + p->off[g], p->Yb + p->off[g], p->Yc ? p->Yc + p->off[g] : nullptr,
+                       p->Yd ? p->Yd + p->off[g] : nullptr};
     const size_t rs = p->precision == RKL_MIXED ? sizeof(float) : sizeof(double);
     void* M = (char*)p->MY0 + rs * p->off[g];
     const GridState* gs = p->state + g;
     // stage 1: Y1 = Y0 + mut_1 tau M(Y0), tau M(Y0) kept for the later stages
-    HIPCHECK(launch_stage(p->precision, p->variant, gc, 1, 1, T, nullptr, nullptr, nullptr, M, A, b, gs, p->coef, s),
+    HIPCHECK(launch_stage(p->precision, v, gc, 1, 1, T, nullptr, nullptr, nullptr, M, bufs[0], b, gs, p->coef, s),
              "stage 1 launch");
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (p->prof) {
-        HIPCHECK(hipEventCreate(&e0), "event create");
-        HIPCHECK(hipEventCreate(&e1), "event create");
-        p->ev.push_back(e0);
-        p->ev.push_back(e1);
-        HIPCHECK(hipEventRecord(e0, s), "event record");
-    }
-    const double* ym1 = A;
+    // a stage buffer holding neither Y_{j-1} nor Y_{j-2}
+    auto pick = [&](const double* u, const double* w, const double* x) -> double* {
+        for (double* c : bufs)
+            if (c && c != u && c != w && c != x) return c;
+        return nullptr;
+    };
+    const double* ym1 = bufs[0];
     const double* ym2 = T;
-    for (int j = 2; j <= S; ++j) {
-        double* out = j == S ? T : (j == 2 ? B : const_cast<double*>(ym2));
-        HIPCHECK(launch_stage(p->precision, p->variant, gc, 2, j, ym1, ym2, T, M, nullptr, out, b, gs, p->coef, s),
-                 "stage launch");
-        ym2 = ym1;
-        ym1 = out;
-    }
-    if (p->prof) {
-        HIPCHECK(hipEventRecord(e1, s), "event record");
-        p->prof_launches += S - 1;
-        p->prof_cells += (int64_t)(S - 1) * (p->off[g + 1] - p->off[g]);
+    int j = 2;
+    while (j <= S) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (p->prof) {
+            HIPCHECK(hipEventCreate(&e0), "event create");
+            HIPCHECK(hipEventCreate(&e1), "event create");
+            HIPCHECK(hipEventRecord(e0, s), "event record");
+        }
+        int done;
+        if (v.fuse == 2 && j + 1 < S) {
+            // stages j, j+1 in one launch; the final stage always runs alone
+            // (it writes T, which the fused kernel reads around its tiles)
+            double* o1 = pick(ym1, ym2, nullptr);
+            double* o2 = pick(ym1, ym2, o1);
+            HIPCHECK(launch_fused2(v, gc, j, ym1, ym2, T, M, o1, o2, b, gs, p->coef, s), "fused stage launch");
+            ym2 = o1;
+            ym1 = o2;
+            done = 2;
+        } else {
+            // Y_j overwrites Y_{j-2} cell by cell (never Y0 = T before the last stage)
+            double* out = j == S ? T : (ym2 == T ? pick(ym1, T, nullptr) : const_cast<double*>(ym2));
+            HIPCHECK(launch_stage(p->precision, v, gc, 2, j, ym1, ym2, T, M, nullptr, out, b, gs, p->coef, s),
+                     "stage launch");
+            ym2 = ym1;
+            ym1 = out;
+            done = 1;
+        }
+        if (p->prof) {
+            HIPCHECK(hipEventRecord(e1, s), "event record");
+            p->prof_recs.push_back({e0, e1, done, done * n});
+        }
+        j += done;
     }
     return RKL_OK;
 }
@@ -365,7 +432,9 @@ rkl_status rkl_autotune(rkl_plan_t p, int32_t g, const double* T, const void* b,
         res = fail(RKL_EDEVICE, "autotune events");
     }
     for (int v = 0; res == RKL_OK && v < variant_count(); ++v) {
-        p->variant = v;
+        if (variant_get(v).fuse == 2 && !fused_ok(p)) continue;
+        res = select_variant(p, v);
+        if (res != RKL_OK) break;
         // one untimed super-step from the caller's T, then reps timed ones
         if (hipMemcpyAsync(W, T, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) { res = fail(RKL_EDEVICE, "autotune copy"); break; }
         res = rkl_superstep(p, g, W, b, dt_hyp, nullptr, stream);
@@ -402,18 +471,23 @@ rkl_status rkl_profile(rkl_plan_t p, int32_t enable) {
     return RKL_OK;
 }
 
-rkl_status rkl_profile_read(rkl_plan_t p, double* ms, int64_t* launches, int64_t* cells) {
+rkl_status rkl_profile_read(rkl_plan_t p, int32_t fuse, double* ms, int64_t* launches, int64_t* cells) {
     if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (fuse != 1 && fuse != 2) return fail(RKL_EINVAL, "fuse must be 1 or 2");
     double tot = 0.0;
-    for (size_t i = 0; i + 1 < p->ev.size(); i += 2) {
-        HIPCHECK(hipEventSynchronize(p->ev[i + 1]), "event sync");
+    int64_t nl = 0, nc = 0;
+    for (const auto& r : p->prof_recs) {
+        if (r.fuse != fuse) continue;
+        HIPCHECK(hipEventSynchronize(r.b), "event sync");
         float t = 0.f;
-        HIPCHECK(hipEventElapsedTime(&t, p->ev[i], p->ev[i + 1]), "event elapsed");
+        HIPCHECK(hipEventElapsedTime(&t, r.a, r.b), "event elapsed");
         tot += t;
+        nl += 1;
+        nc += r.cells;
     }
     if (ms) *ms = tot;
-    if (launches) *launches = p->prof_launches;
-    if (cells) *cells = p->prof_cells;
+    if (launches) *launches = nl;
+    if (cells) *cells = nc;
     return RKL_OK;
 }
 

@@ -42,12 +42,6 @@ struct BatchPlan {
     int2* items_dev = nullptr;    // device, item -> (grid, tile), largest grids first
 };
 
-__device__ __forceinline__ int xcd_remap_b(int b, int nb) {
-    const int q = nb / 8, r = nb % 8;
-    const int xcd = b % 8, slot = b / 8;
-    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-}
-
 // one workgroup per grid: extrema of T, then dt_par and s for that grid
 __global__ __launch_bounds__(kBT) void batch_reduce_kernel(const BatchGrid* __restrict__ grids,
                                                            const double* __restrict__ T,
@@ -164,7 +158,7 @@ template <typename R, bool LIM, bool SAT, int KM>
 __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int2* __restrict__ items,
                                                           int stage) {
     __shared__ TileLds<R, kPL, kFX, kFY> L;
-    const int2 it = items[xcd_remap_b(blockIdx.x, gridDim.x)];
+    const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const GridState st = P.state[it.x];
     if (st.s < stage || (st.flags & RKL_FLAG_STAGES)) return;   // uniform over the block
     batch_tile<R, LIM, SAT, KM>(P, it.x, stage, it.y, st, L);

@@ -71,9 +71,10 @@ __device__ inline GridState finalize_state(const GridConst& g, double mx, double
     return o;
 }
 
-// Kernel variants of the single-grid stencil: tile shape and z-chunk length.
+// Kernel variants of the single-grid stencil: tile shape, z-chunk length and
+// stages per launch (1, or 2 for the fused kernel).
 struct Variant {
-    int bx, by, bz;
+    int bx, by, bz, fuse;
 };
 int variant_count();
 Variant variant_get(int v);
@@ -84,9 +85,14 @@ int reduce_blocks(int64_t N);
 hipError_t launch_finalize(const double* partials, int nblocks, const GridConst& gc, double dt_hyp,
                            int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st);
 // kind: 0 flux divergence into Yout, 1 first stage, 2 stage j >= 2
-hipError_t launch_stage(int precision, int variant, const GridConst& gc, int kind, int stage,
+hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind, int stage,
                         const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
                         const double* coef, hipStream_t st);
+// stages j and j+1 (2 <= j, j+1 < s) in one launch, RKL_MIXED and 3-D grids
+// only; Yj and Yj1 must alias none of Yin, Ym2, Y0
+hipError_t launch_fused2(Variant v, const GridConst& gc, int stage, const double* Yin, const double* Ym2,
+                         const double* Y0, const void* MY0, double* Yj, double* Yj1, const void* b,
+                         const GridState* state, const double* coef, hipStream_t st);
 
 }  // namespace rkl

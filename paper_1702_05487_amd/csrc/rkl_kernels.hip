@@ -10,22 +10,16 @@
 namespace rkl {
 
 // ------------------------------------------------------------ variants ----
-// (bx, by) are compile-time tile shapes; bz is the z-chunk length per block.
+// (bx, by) are compile-time tile shapes; bz is the z-chunk length per block;
+// fuse is the number of stages per launch (2: rkl_fused.hip, where (bx, by)
+// is the region of a workgroup and (bx-2, by-2) its output tile).
 static const Variant kVariants[] = {
-    {32, 8, 32}, {32, 8, 64}, {64, 4, 32}, {64, 4, 64}, {16, 16, 32}, {16, 16, 64},
-    {32, 8, 16}, {64, 4, 16},
+    {32, 8, 32, 1}, {32, 8, 64, 1}, {64, 4, 32, 1}, {64, 4, 64, 1}, {16, 16, 32, 1}, {16, 16, 64, 1},
+    {32, 8, 16, 1}, {64, 4, 16, 1},
+    {16, 16, 32, 2}, {16, 16, 64, 2}, {32, 8, 32, 2}, {32, 8, 64, 2},
 };
 int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 Variant variant_get(int v) { return kVariants[v]; }
-
-// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that
-// consecutive logical tiles (which share halo lines) land on the same XCD and
-// its L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    const int q = nb / 8, r = nb % 8;
-    const int xcd = b % 8, slot = b / 8;
-    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-}
 
 // ----------------------------------------------------------- reduction ----
 // per-block maximum, minimum and a non-finite flag of T
@@ -177,11 +171,10 @@ static hipError_t launch_prec(const StageLaunch& P, int nblocks, int bx, int by,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_stage(int precision, int variant, const GridConst& gc, int kind, int stage,
+hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind, int stage,
                         const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
                         const double* coef, hipStream_t st) {
-    const Variant v = variant_get(variant);
     StageLaunch P;
     TileArgs& a = P.t;
     a.Yin = Yin;

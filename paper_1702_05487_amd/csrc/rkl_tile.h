@@ -162,6 +162,15 @@ struct TileLds {
     R FY[2][FYMAX];     // y-face fluxes, [by+1][bx]
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so that
+// consecutive logical tiles (which share halo lines) land on the same XCD and
+// its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb / 8, r = nb % 8;
+    const int xcd = b % 8, slot = b / 8;
+    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
 __device__ __forceinline__ int wrap(int i, int n) {
     int m = i % n;
     return m < 0 ? m + n : m;

@@ -88,11 +88,11 @@ def load(build_if_missing: bool = True):
         "rkl_graph_launch": (i32, [vp, vp]),
         "rkl_query": (i32, [vp, i32, P(i32), P(dbl), P(ctypes.c_uint32)]),
         "rkl_variant_count": (i32, []),
-        "rkl_variant_info": (i32, [i32, P(i32), P(i32), P(i32)]),
+        "rkl_variant_info": (i32, [i32, P(i32), P(i32), P(i32), P(i32)]),
         "rkl_set_variant": (i32, [vp, i32]),
         "rkl_last_error": (ctypes.c_char_p, []),
         "rkl_profile": (i32, [vp, i32]),
-        "rkl_profile_read": (i32, [vp, P(dbl), P(i64), P(i64)]),
+        "rkl_profile_read": (i32, [vp, i32, P(dbl), P(i64), P(i64)]),
         "rkl_autotune": (i32, [vp, i32, vp, vp, dbl, i32, P(i32), P(dbl), vp]),
     }
     for name, (res, args) in sig.items():
@@ -164,9 +164,10 @@ def rkl_variant_count():
 
 
 def rkl_variant_info(v):
-    x, y, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(load().rkl_variant_info(v, ctypes.byref(x), ctypes.byref(y), ctypes.byref(z)))
-    return x.value, y.value, z.value
+    """(tile_x, tile_y, tile_z, stages per launch) of variant v."""
+    x, y, z, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().rkl_variant_info(v, ctypes.byref(x), ctypes.byref(y), ctypes.byref(z), ctypes.byref(f)))
+    return x.value, y.value, z.value, f.value
 
 
 def rkl_set_variant(plan, v):
@@ -188,9 +189,9 @@ def rkl_profile(plan, enable):
     _check(load().rkl_profile(plan, int(enable)))
 
 
-def rkl_profile_read(plan):
+def rkl_profile_read(plan, fuse=1):
     ms, n, c = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
-    _check(load().rkl_profile_read(plan, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(c)))
+    _check(load().rkl_profile_read(plan, int(fuse), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(c)))
     return ms.value, n.value, c.value
 
 

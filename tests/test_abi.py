@@ -73,8 +73,13 @@ def test_invalid_options_are_rejected():
 def test_variant_table():
     n = rkl.rkl_variant_count()
     assert n >= 3
+    fuses = set()
     for v in range(n):
-        bx, by, bz = rkl.rkl_variant_info(v)
-        assert bx * by <= 1024 and bz >= 1
+        bx, by, bz, fuse = rkl.rkl_variant_info(v)
+        assert bx * by <= 1024 and bz >= 1 and fuse in (1, 2)
+        fuses.add(fuse)
+        if fuse == 2:
+            assert bx >= 3 and by >= 3   # the output tile is (bx-2) x (by-2)
+    assert fuses == {1, 2}
     with pytest.raises(rkl.RklError):
         rkl.rkl_variant_info(n)
