@@ -332,10 +332,10 @@ __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& f
             const R* FY = L.FY1[fb];
             const int fx = ty * (BX + 1) + tx;
             R div = (FX[fx + 1] - FX[fx]) * ih0;
-            div += (FY[(ty + 1) * BX + tx] - FY[ty * BX + tx]) * ih1;
-            div += (fzn - fzp) * ih2;
+            div = fma(FY[(ty + 1) * BX + tx] - FY[ty * BX + tx], ih1, div);
+            div = fma(fzn - fzp, ih2, div);
             const double tl = a.scale * (double)div;
-            yj = a.mu1 * yq0 + a.nu1 * ym2 + a.omn1 * y0v + a.mut1 * tl + a.gt1 * (double)my0;
+            yj = stage_combine(a.mu1, a.nu1, a.omn1, a.mut1, a.gt1, yq0, ym2, y0v, tl, (double)my0);
             if (store && K >= z0 && K < z1) a.Yj[(size_t)K * plane + oxy] = yj;
         }
         fzp = fzn;
@@ -345,11 +345,11 @@ __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& f
             const R* FX = L.FX2[fb];
             const R* FY = L.FY2[fb];
             R div = (FX[rslot] - FX[rslot - 1]) * ih0;
-            div += (FY[rslot] - FY[rslot - BX]) * ih1;
-            div += (gzn - gzp) * ih2;
+            div = fma(FY[rslot] - FY[rslot - BX], ih1, div);
+            div = fma(gzn - gzp, ih2, div);
             const double tl = a.scale * (double)div;
             a.Yj1[(size_t)k2 * plane + oxy] =
-                a.mu2 * uq0 + a.nu2 * dy3 + a.omn2 * dz3 + a.mut2 * tl + a.gt2 * (double)dm3;
+                stage_combine(a.mu2, a.nu2, a.omn2, a.mut2, a.gt2, uq0, dy3, dz3, tl, (double)dm3);
         }
         gzp = gzn;
 

@@ -104,7 +104,8 @@ struct StageLaunch {
     double fac;
 };
 
-template <typename R, bool LIM, bool SAT, int KM, int BX, int BY>
+// FIX3: 3-D grid, tile shape fixed at compile time (run_tile's CBX, CBY)
+template <typename R, bool LIM, bool SAT, int KM, int BX, int BY, bool FIX3>
 __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
     constexpr int PL = (BX + 2) * (BY + 2);
     __shared__ TileLds<R, PL, (BX + 1) * BY, BX*(BY + 1)> L;
@@ -143,15 +144,24 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
     fk.kperp = R(P.kperp);
     fk.satq = R(P.satq);
     fk.tref = R(tref);
-    run_tile<R, LIM, SAT, KM>(a, fk, tref, L);
+    if constexpr (FIX3)
+        run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), BX, BY>(a, fk, tref, L);
+    else
+        run_tile<R, LIM, SAT, KM>(a, fk, tref, L);
+}
+
+template <typename R, int KM, int BX, int BY, bool FIX3>
+static void launch_fix(const StageLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
+    if (lim && sat) stage_kernel<R, true, true, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
+    else if (lim) stage_kernel<R, true, false, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
+    else if (sat) stage_kernel<R, false, true, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
+    else stage_kernel<R, false, false, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
 }
 
 template <typename R, int KM, int BX, int BY>
 static void launch_km(const StageLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
-    if (lim && sat) stage_kernel<R, true, true, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (lim) stage_kernel<R, true, false, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (sat) stage_kernel<R, false, true, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
-    else stage_kernel<R, false, false, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    if (P.t.ndim == 3) launch_fix<R, KM, BX, BY, true>(P, nblocks, lim, sat, st);
+    else launch_fix<R, KM, BX, BY, false>(P, nblocks, lim, sat, st);
 }
 
 template <typename R, int BX, int BY>

@@ -28,6 +28,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// No automatic contraction of a*b+c: every fused multiply-add below is
+// written out, so each tile shape, kernel variant and the batched kernels
+// (different instantiations of the same code) round identically.
+#pragma clang fp contract(off)
+
 namespace rkl {
 
 // ---------------------------------------------------------------- math ----
@@ -113,20 +118,20 @@ __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R
     const R Gn = (TR - TL) * ihn;
     const R G1 = face_transverse<R, LIM>(sL1, sR1);
     const R G2 = face_transverse<R, LIM>(sL2, sR2);
-    const R Tf = fmax(R(0.5) * (TL + TR) + k.tref, R(1e-30));
+    const R Tf = fmax(fma(R(0.5), TL + TR, k.tref), R(1e-30));
     const R rs = (SAT || KM == 1) ? r_rsqrt(Tf) : R(0);
     const R T2 = Tf * Tf;
     const R kpar = KM == 0 ? k.kappa0 : (KM == 1 ? k.kappa0 * (T2 * Tf * rs) : k.kappa0 * r_pow(Tf, k.kexp));
     const R kperp = k.kperp * kpar;
     const R cn = bLn + bRn, c1 = bL1 + bR1, c2 = bL2 + bR2;
-    const R cc = cn * cn + c1 * c1 + c2 * c2;
-    const R cG = cn * Gn + c1 * G1 + c2 * G2;
+    const R cc = fma(cn, cn, fma(c1, c1, c2 * c2));
+    const R cG = fma(cn, Gn, fma(c1, G1, c2 * G2));
     const R w = cc < R(1e-24) ? R(0) : cG * r_rcp(cc);     // (b.G)/|c|
     const R dk = kpar - kperp;
-    R Fn = -(kperp * Gn + dk * (cn * w));
+    R Fn = -fma(kperp, Gn, dk * (cn * w));
     if (SAT) {
-        const R GG = Gn * Gn + G1 * G1 + G2 * G2;
-        const R F2 = kperp * kperp * GG + dk * (kpar + kperp) * (cG * w);
+        const R GG = fma(Gn, Gn, fma(G1, G1, G2 * G2));
+        const R F2 = fma(kperp * kperp, GG, dk * (kpar + kperp) * (cG * w));
         const R Fm = r_sqrt(fmax(F2, R(0)));
         const R q = k.satq * (T2 * rs);
         const R qF = q + Fm;
@@ -181,11 +186,24 @@ __device__ __forceinline__ R to_r(double v, double tref) {
     return R(v - tref);
 }
 
-template <typename R, bool LIM, bool SAT, int KM, int PLMAX, int FXMAX, int FYMAX>
+// the RKL2 stage recurrence, Appendix A:
+// mu Y_{j-1} + nu Y_{j-2} + (1-mu-nu) Y0 + mut tau M(Y_{j-1}) + gt tau M(Y0)
+__device__ __forceinline__ double stage_combine(double mu, double nu, double omn, double mut, double gt,
+                                                double ym1, double ym2, double y0, double tl, double my0) {
+    return fma(gt, my0, fma(mut, tl, fma(omn, y0, fma(nu, ym2, mu * ym1))));
+}
+
+// CBX, CBY > 0: the tile shape is a compile-time constant, the grid is 3-D
+// and the workgroup has exactly CBX*CBY threads (one cell each); the tile
+// strides are then constants and the face code has no runtime branches.
+template <typename R, bool LIM, bool SAT, int KM, int PLMAX, int FXMAX, int FYMAX, int CBX = 0, int CBY = 0>
 __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, double tref,
                                          TileLds<R, PLMAX, FXMAX, FYMAX>& L) {
+    constexpr bool FIX = CBX > 0;
+    static_assert(!FIX || (2 * CBX + 2 * CBY + 4 <= CBX * CBY && CBX + CBY <= CBX * CBY),
+                  "the ring cells and extra faces need one thread each");
     const int tid = threadIdx.x;
-    const int bx = a.bx, by = a.by, px = bx + 2;
+    const int bx = FIX ? CBX : a.bx, by = FIX ? CBY : a.by, px = bx + 2;
     const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
     const int plane = n0 * n1;
     const size_t N = (size_t)plane * (size_t)n2;
@@ -194,10 +212,10 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     const R* b2 = b1 + N;
     const R ih0 = R(a.ih0), ih1 = R(a.ih1), ih2 = R(a.ih2);
     const R hih0 = R(0.5 * a.ih0), hih1 = R(0.5 * a.ih1), hih2 = R(0.5 * a.ih2);
-    const bool do_y = a.ndim >= 2, do_z = a.ndim >= 3;
+    const bool do_y = FIX || a.ndim >= 2, do_z = FIX || a.ndim >= 3;
 
     // own cell of this thread
-    const bool own = tid < bx * by;
+    const bool own = FIX || tid < bx * by;
     const int tx = own ? tid % bx : 0, ty = own ? tid / bx : 0;
     const int oslot = (ty + 1) * px + tx + 1;
     const int oxy = wrap(a.y0 + ty, n1) * n0 + wrap(a.x0 + tx, n0);
@@ -231,7 +249,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     // sit in the first ones, so that no wave carries both (wave w of every
     // workgroup runs on the same SIMD).
     const int nf = by + (do_y ? bx : 0);
-    const int fbase = max(0, ((int)blockDim.x - nf) / 64 * 64);
+    const int fbase = max(0, ((FIX ? CBX * CBY : (int)blockDim.x) - nf) / 64 * 64);
     const int fid = tid - fbase;
     const bool fjob = fid >= 0 && fid < nf;
     int fdir = 0, fL = 0, fR = 0, fidx = 0;
@@ -406,8 +424,8 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
             const R* FY = L.FY[fb];
             const int fx = ty * (bx + 1) + tx;
             R div = (FX[fx + 1] - FX[fx]) * ih0;
-            if (do_y) div += (FY[(ty + 1) * bx + tx] - FY[ty * bx + tx]) * ih1;
-            if (do_z) div += (fzn - fzp) * ih2;
+            if (do_y) div = fma(FY[(ty + 1) * bx + tx] - FY[ty * bx + tx], ih1, div);
+            if (do_z) div = fma(fzn - fzp, ih2, div);
             const size_t o = (size_t)k * plane + oxy;
             const double tl = a.scale * (double)div;
             if (a.kind == 0) {
@@ -415,9 +433,9 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
             } else if (a.kind == 1) {
                 const R m = R(tl);
                 ((R*)a.MY0out)[o] = m;
-                a.Yout[o] = yq0 + a.mut * (double)m;
+                a.Yout[o] = fma(a.mut, (double)m, yq0);
             } else {
-                a.Yout[o] = a.mu * yq0 + a.nu * ym2 + a.omn * y0v + a.mut * tl + a.gt * (double)my0;
+                a.Yout[o] = stage_combine(a.mu, a.nu, a.omn, a.mut, a.gt, yq0, ym2, y0v, tl, (double)my0);
             }
         }
         fzp = fzn;

@@ -146,6 +146,16 @@ def test_superstep_every_variant(torch_cuda, variant):
     assert rel_l1(g, o) <= 1e-12
 
 
+def test_every_variant_gives_the_same_bits(torch_cuda):
+    """Each variant computes every face once, with the same operations in the
+    same order (no automatic contraction), so the tile shape chosen by the
+    autotuner never changes the result."""
+    ref, _, _ = superstep_pair(torch_cuda, "tangled_mc_sat", "fp64", 1, inputs.midpoint_ratio(6), 0)
+    for v in range(1, 8):
+        g, _, _ = superstep_pair(torch_cuda, "tangled_mc_sat", "fp64", 1, inputs.midpoint_ratio(6), v)
+        assert np.array_equal(g, ref), v
+
+
 def test_superstep_is_deterministic(torch_cuda):
     torch = torch_cuda
     n, h, ndim, p, T, b = make_case("tangled_mc")
