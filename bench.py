@@ -71,16 +71,89 @@ def traffic_for(name, precision, fuse):
     return d.get("bytes_per_launch")
 
 
+def summarize_counters(fetch_csv, write_csv, workload, precision, fuse):
+    """HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc
+    runs of this script with --copy-calibration (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch).  Each counter is scaled by the factor that
+    makes it read 1 GiB for the plain 1 GiB device copy that starts the
+    calibration run.  Stage-1 launches (the first stencil launch after each finalize
+    launch) are left out: the measured kernel is stages j >= 2.  Writes the
+    JSON that traffic_for reads and returns it."""
+    import csv
+
+    def per_dispatch(path, counter):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            d = int(r["Dispatch_Id"])
+            name, v = out.get(d, (r["Kernel_Name"], 0.0))
+            out[d] = (name, v + float(r["Counter_Value"]))
+        return out
+
+    def measured(disp):
+        # the calibration copy is the run's first device copy
+        copies = [disp[d][1] for d in sorted(disp) if "copyBuffer" in disp[d][0]]
+        if not copies:
+            raise SystemExit("no copy-calibration dispatch in the counter file")
+        vals, after_finalize = [], False
+        for d in sorted(disp):
+            name, v = disp[d]
+            if "finalize_kernel" in name:
+                after_finalize = True
+                continue
+            if KERNEL_NAMES[fuse] in name:
+                if not (fuse == 1 and after_finalize):
+                    vals.append(v)
+                after_finalize = False
+        if not vals:
+            raise SystemExit("no %s dispatch in the counter file" % KERNEL_NAMES[fuse])
+        return sum(vals) / len(vals), copies[0], len(vals)
+
+    f_k, f_copy, nf = measured(per_dispatch(fetch_csv, "FETCH_SIZE"))
+    w_k, w_copy, nw = measured(per_dispatch(write_csv, "WRITE_SIZE"))
+    gib_kib = float(1 << 20)
+    ff, wf = gib_kib / f_copy, gib_kib / w_copy
+    rd, wr = f_k * ff * 1024.0, w_k * wf * 1024.0
+    d = {"kernel": KERNEL_NAMES[fuse], "workload": workload, "precision": precision,
+         "kernel_hash": kernel_hash(fuse), "fetch_factor": ff, "write_factor": wf,
+         "read_bytes_per_launch": rd, "write_bytes_per_launch": wr, "bytes_per_launch": rd + wr,
+         "dispatches": [nf, nw]}
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.json" % (KERNEL_NAMES[fuse], workload, precision))
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1)
+        fh.write("\n")
+    return d
+
+
+def copy_ceiling(torch):
+    """Bandwidth of a plain 1 GiB device-to-device copy (read + write bytes
+    per second), measured on the same GPU for reference."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    return gbs
+
+
 def cpu_baseline(w, T0, b, s, dt):
     """The oracle, untuned, on a bounded sample of the same workload: one
     super-step (s stages) of a 256 x 256 x 16 periodic slab cut from the same
-    fields, on one host core."""
+    fields (host arrays T0 [16][256][256], b [3][16][256][256]), on one host
+    core."""
     import numpy as np
     import oracle
     nz = 16
     m = 256
-    T = np.ascontiguousarray(T0[:nz, :m, :m].cpu().numpy())
-    b = np.ascontiguousarray(b[:, :nz, :m, :m].double().cpu().numpy())
+    T = np.ascontiguousarray(T0)
+    b = np.ascontiguousarray(b)
     g = oracle.Grid(n=(m, m, nz), h=w.h, ndim=3, **w.params)
     t0 = time.perf_counter()
     oracle.rkl2_fixed(g, T, b, s, dt)
@@ -101,7 +174,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (reference for HBM counters)")
+    ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic JSON of --workload/--variant from two rocprofv3 counter files")
+    ap.add_argument("--fuse", type=int, default=1, help="stages per launch of the kernel summarized")
     args = ap.parse_args()
+    if args.counters_summary:
+        print(json.dumps(summarize_counters(*args.counters_summary, args.workload,
+                                            WORKLOADS[args.workload][1], args.fuse)))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
               file=sys.stderr)
@@ -124,7 +204,7 @@ def main():
     dev = torch.device("cuda:0")
     w = getattr(inputs, builder)(device=dev)       # fields generated on the GPU
     plan = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision=precision)
-    T0 = w.T
+    T0, w.T = w.T, None
     bdev = w.b.to(dtype=torch.float32 if precision == "mixed" else torch.float64)
     w.b = None
     T = T0.clone()
@@ -156,6 +236,9 @@ def main():
     ms, launches, cell_stages = rkl.rkl_profile_read(plan.handle, fuse)
     rkl.rkl_profile(plan.handle, 0)
     s_last = plan.query()[0]
+    # host copies of a 256 x 256 x 16 slab for the CPU baseline
+    T0_host = T0[:16, :256, :256].cpu().numpy()
+    b_host = bdev[:, :16, :256, :256].double().cpu().numpy()
 
     avg_launch_s = ms / 1e3 / launches
     bytes_per_launch = bytes_per_cs * cells * fuse
@@ -189,10 +272,15 @@ def main():
             "kernel_cell_stage_per_s": cell_stages / (ms / 1e3),
         },
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, T0, bdev, s_last, dt)
-    print(json.dumps(out), flush=True)
     plan.close()
+    del T, T0, bdev
+    torch.cuda.empty_cache()
+    ceil = copy_ceiling(torch)
+    out["roofline"]["copy_GBs"] = ceil
+    out["roofline"]["frac_of_copy"] = achieved / ceil
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, T0_host, b_host, s_last, dt)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

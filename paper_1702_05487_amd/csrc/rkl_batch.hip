@@ -145,12 +145,7 @@ __device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int
     }
     a.Yout = j == st.s ? Tg : ((j & 1) ? A : B);
     const double tref = sizeof(R) == 4 ? st.tref : 0.0;
-    FaceK<R> fk;
-    fk.kappa0 = R(G.gc.kappa0);
-    fk.kexp = R(G.gc.kexp);
-    fk.kperp = R(G.gc.kperp);
-    fk.satq = R(G.gc.satq);
-    fk.tref = R(tref);
+    const FaceK<R> fk = make_facek<R>(G.gc.kappa0, G.gc.kexp, G.gc.kperp, G.gc.satq, tref);
     run_tile<R, LIM, SAT, KM>(a, fk, tref, L);
 }
 

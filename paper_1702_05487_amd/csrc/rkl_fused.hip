@@ -40,12 +40,7 @@ __global__ __launch_bounds__(BX* BY) void fused2_kernel(FusedLaunch P) {
     a.mu1 = c1[0]; a.nu1 = c1[1]; a.omn1 = c1[2]; a.mut1 = c1[3]; a.gt1 = c1[4];
     a.mu2 = c2[0]; a.nu2 = c2[1]; a.omn2 = c2[2]; a.mut2 = c2[3]; a.gt2 = c2[4];
     a.scale = -st->cdiv;
-    FaceK<float> fk;
-    fk.kappa0 = float(P.kappa0);
-    fk.kexp = float(P.kexp);
-    fk.kperp = float(P.kperp);
-    fk.satq = float(P.satq);
-    fk.tref = float(tref);
+    const FaceK<float> fk = make_facek<float>(P.kappa0, P.kexp, P.kperp, P.satq, tref);
     run_fused2<float, LIM, SAT, KM, BX, BY>(a, fk, tref, L);
 }
 

@@ -138,12 +138,7 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
         a.gt = cf[4];
         a.scale = -st->cdiv;
     }
-    FaceK<R> fk;
-    fk.kappa0 = R(P.kappa0);
-    fk.kexp = R(P.kexp);
-    fk.kperp = R(P.kperp);
-    fk.satq = R(P.satq);
-    fk.tref = R(tref);
+    const FaceK<R> fk = make_facek<R>(P.kappa0, P.kexp, P.kperp, P.satq, tref);
     if constexpr (FIX3)
         run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), BX, BY>(a, fk, tref, L);
     else

@@ -93,9 +93,27 @@ __device__ __forceinline__ R face_transverse(R sL, R sR) {
 // per-grid constants of the face flux, in the flux precision
 template <typename R>
 struct FaceK {
-    R kappa0, kexp, kperp, satq;  // satq = 5 phi rho
-    R tref;                       // added back to offset temperatures
+    R kappa0, kexp;
+    R r, omr;       // kappa_perp / kappa_par and 1 - r
+    R r2, omr2;     // r^2 and 1 - r^2
+    R satq;         // 5 phi rho
+    R tref;         // added back to offset temperatures
 };
+
+template <typename R>
+__device__ __forceinline__ FaceK<R> make_facek(double kappa0, double kexp, double kperp_ratio, double satq,
+                                              double tref) {
+    FaceK<R> k;
+    k.kappa0 = R(kappa0);
+    k.kexp = R(kexp);
+    k.r = R(kperp_ratio);
+    k.omr = R(1.0 - kperp_ratio);
+    k.r2 = R(kperp_ratio * kperp_ratio);
+    k.omr2 = R(1.0 - kperp_ratio * kperp_ratio);
+    k.satq = R(satq);
+    k.tref = R(tref);
+    return k;
+}
 
 // Normal component of F_c through a face, for cells L (low) and R (high)
 // along the face normal.  s?1, s?2: the cells' slopes along the two
@@ -104,13 +122,16 @@ struct FaceK {
 // T^2.5, 2 kappa0 T^kexp.
 //
 // With c = b_L + b_R the face direction is c/|c| (0 if |c| < 1e-12), so
-// b_n (b.G) = c_n (c.G)/|c|^2, and the magnitude of the classical flux
-// -[k_perp G + (k_par-k_perp) b (b.G)] follows from
-// |F|^2 = k_perp^2 |G|^2 + (k_par^2 - k_perp^2) (b.G)^2.
-// kappa_par = kappa0 T^2.5 is evaluated as kappa0 T^3 / sqrt(T) and the
-// saturated flux 5 phi rho T^1.5 as satq T^2 / sqrt(T) (one reciprocal root;
-// T is clipped at 1e-30 instead of 0 so that the root stays finite, which
-// changes kappa and q by less than 1e-75).
+// b_n (b.G) = c_n w and (b.G)^2 = (c.G) w with w = (c.G)/|c|^2.  With
+// kappa_perp = r kappa_par the classical flux is
+//   F = -kappa_par [r G + (1-r) b (b.G)],   F_n = -kappa_par A,
+//   A = r G_n + (1-r) c_n w,
+//   |F| = kappa_par B,   B^2 = r^2 |G|^2 + (1-r^2) (b.G)^2,
+// and the saturated blend q F/(q + |F|) is -kappa_par A q / (q + kappa_par B).
+// kappa_par = kappa0 T^2.5 is evaluated as kappa0 T (T^2/sqrt(T)) and the
+// saturated flux 5 phi rho T^1.5 as satq T^2/sqrt(T) with the same T^1.5
+// (one reciprocal root; T is clipped at 1e-30 instead of 0 so that the root
+// stays finite, which changes kappa and q by less than 1e-75).
 template <typename R, bool LIM, bool SAT, int KM>
 __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R sR2,
                                        R bLn, R bL1, R bL2, R bRn, R bR1, R bR2,
@@ -119,25 +140,19 @@ __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R
     const R G1 = face_transverse<R, LIM>(sL1, sR1);
     const R G2 = face_transverse<R, LIM>(sL2, sR2);
     const R Tf = fmax(fma(R(0.5), TL + TR, k.tref), R(1e-30));
-    const R rs = (SAT || KM == 1) ? r_rsqrt(Tf) : R(0);
-    const R T2 = Tf * Tf;
-    const R kpar = KM == 0 ? k.kappa0 : (KM == 1 ? k.kappa0 * (T2 * Tf * rs) : k.kappa0 * r_pow(Tf, k.kexp));
-    const R kperp = k.kperp * kpar;
+    const R t15 = (SAT || KM == 1) ? (Tf * Tf) * r_rsqrt(Tf) : R(0);   // T^1.5
+    const R kpar = KM == 0 ? k.kappa0 : (KM == 1 ? k.kappa0 * (t15 * Tf) : k.kappa0 * r_pow(Tf, k.kexp));
     const R cn = bLn + bRn, c1 = bL1 + bR1, c2 = bL2 + bR2;
     const R cc = fma(cn, cn, fma(c1, c1, c2 * c2));
     const R cG = fma(cn, Gn, fma(c1, G1, c2 * G2));
     const R w = cc < R(1e-24) ? R(0) : cG * r_rcp(cc);     // (b.G)/|c|
-    const R dk = kpar - kperp;
-    R Fn = -fma(kperp, Gn, dk * (cn * w));
-    if (SAT) {
-        const R GG = fma(Gn, Gn, fma(G1, G1, G2 * G2));
-        const R F2 = fma(kperp * kperp, GG, dk * (kpar + kperp) * (cG * w));
-        const R Fm = r_sqrt(fmax(F2, R(0)));
-        const R q = k.satq * (T2 * rs);
-        const R qF = q + Fm;
-        Fn = qF > R(0) ? Fn * (q * r_rcp(qF)) : R(0);
-    }
-    return Fn;
+    const R A = fma(k.r, Gn, k.omr * (cn * w));
+    if (!SAT) return -(kpar * A);
+    const R GG = fma(Gn, Gn, fma(G1, G1, G2 * G2));
+    const R B2 = fma(k.r2, GG, k.omr2 * (cG * w));
+    const R q = k.satq * t15;
+    const R den = fma(kpar, r_sqrt(fmax(B2, R(0))), q);    // q + |F|
+    return den > R(0) ? -(kpar * A) * (q * r_rcp(den)) : R(0);
 }
 
 // ------------------------------------------------------------- one tile ----
