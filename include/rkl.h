@@ -193,10 +193,12 @@ rkl_status rkl_set_variant(rkl_plan_t plan, int32_t variant);
 /*
  * Kernel timing for benchmarks.  rkl_profile(plan, 1) starts recording, with
  * a pair of HIP events on the caller's stream around each stencil launch of
- * stages j >= 2 of every following rkl_superstep (the dominant kernels);
- * rkl_profile(plan, 0) stops and discards.  rkl_profile_read synchronises
- * and returns, over the launches with `fuse` stages each (1 or 2), the summed
- * duration in ms, the number of launches and of cell-stage updates.
+ * stages j >= 2 of every following rkl_superstep and (eager, not captured)
+ * rkl_superstep_batched (the dominant kernels); rkl_profile(plan, 0) stops
+ * and discards.  rkl_profile_read synchronises and returns, over the
+ * launches with `fuse` stages each (1 or 2), the summed duration in ms, the
+ * number of launches and of cell-stage updates (batched launches count 0
+ * cell-stages: their work follows from the device-side stage counts).
  */
 rkl_status rkl_profile(rkl_plan_t plan, int32_t enable);
 rkl_status rkl_profile_read(rkl_plan_t plan, int32_t fuse, double *ms, int64_t *launches,

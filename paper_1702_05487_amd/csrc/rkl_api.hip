@@ -513,7 +513,11 @@ rkl_status rkl_superstep_batched(rkl_plan_t p, double* T, const void* b, const d
         if (st != RKL_OK) return fail(st, why);
     }
     BatchBuffers bb{T, b, dt_hyp, s_out, p->Ya, p->Yb, p->MY0, p->coef, p->state};
-    hipError_t e = batch_launch(p->batch, bb, (hipStream_t)stream);
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    hipError_t e = batch_launch(p->batch, bb, (hipStream_t)stream, p->prof ? &ev : nullptr);
+    // cell-stages of a batched launch depend on the device-side stage counts:
+    // recorded as 0 (the caller knows them from s_out)
+    for (auto& x : ev) p->prof_recs.push_back({x.first, x.second, 1, 0});
     if (e != hipSuccess) return hipfail(e, "batched launch");
     return RKL_OK;
 }

@@ -1,6 +1,7 @@
 // rkl_batch.h -- the batched (many-grid) super-step of librkl.
 #pragma once
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/rkl.h"
@@ -26,7 +27,10 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
                         const std::vector<int64_t>& off, int precision, int smax, BatchPlan** out,
                         std::string& why);
 void batch_free(BatchPlan* bp);
-// Enqueue one super-step of every grid (no host synchronisation).
-hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st);
+// Enqueue one super-step of every grid (no host synchronisation).  With
+// `events` non-NULL, a pair of HIP events (created here, owned by the caller)
+// is recorded around each launch of stages j >= 2.
+hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st,
+                        std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr);
 
 }  // namespace rkl

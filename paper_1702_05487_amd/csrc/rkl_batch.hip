@@ -261,7 +261,8 @@ static void launch_stage_b(const BatchPlan* bp, const BatchBufs& a, int stage, h
     else launch_stage_km<R, 2>(bp, a, stage, st);
 }
 
-hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st) {
+hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st,
+                        std::vector<std::pair<hipEvent_t, hipEvent_t>>* events) {
     batch_reduce_kernel<<<bp->ngrids, kBT, 0, st>>>(bp->grids, buf.T, buf.dt_hyp, buf.state, buf.s_out,
                                                     bp->smax);
     hipError_t e = hipGetLastError();
@@ -276,10 +277,18 @@ hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st) 
     a.Yb = buf.Yb;
     a.MY0 = buf.MY0;
     for (int j = 1; j <= bp->smax; ++j) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (events && j >= 2) {
+            if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+            if ((e = hipEventCreate(&e1)) != hipSuccess) { hipEventDestroy(e0); return e; }
+            events->push_back({e0, e1});
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
+        }
         if (bp->precision == RKL_MIXED) launch_stage_b<float>(bp, a, j, st);
         else launch_stage_b<double>(bp, a, j, st);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (e1 && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
