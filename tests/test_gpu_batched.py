@@ -158,3 +158,44 @@ def test_batched_stage_limit_is_flagged(torch_cuda):
     assert plan.query(2)[2] & rkl.RKL_FLAG_STAGES
     assert torch.equal(T[off[2]:off[3]], T0[off[2]:off[3]])
     assert not torch.equal(T[off[1]:off[2]], T0[off[1]:off[2]])
+
+
+def test_patches_2000_full_size_sampled(torch_cuda):
+    """The 2000-patch workload at full size in the launch configuration that
+    bench.py times (mixed, smax 48, captured graph replayed): whole patches
+    sampled and compared with the oracle -- the six smallest, two drawn at
+    random and the small patch with the most stages."""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    ps = inputs.patch_set(2000, device="cuda:0")
+    descs = [lib_desc(n, (1 / 64,) * 3, 3, ps.params) for n in ps.n]
+    T0 = torch.cat([t.reshape(-1) for t in ps.T]).contiguous()
+    b = torch.cat([x.reshape(-1) for x in ps.b]).to(torch.float32).contiguous()
+    plan = rkl.Plan(descs, precision="mixed", smax=48)
+    off = plan.offsets()
+    dts = [ps.ratio[p] * plan.dt_par(T0[off[p]:off[p + 1]], grid=p) for p in range(len(descs))]
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
+    s_out = torch.zeros(len(descs), dtype=torch.int32, device="cuda:0")
+    T = T0.clone()
+    plan.graph_capture(T, b, dt, s_out)
+    plan.graph_launch()
+    s = s_out.cpu().numpy()
+    assert s.min() >= 4 and s.max() <= 40
+    cells = np.array(ps.cells)
+    order = np.argsort(cells)
+    rng = np.random.default_rng(17)
+    small = order[cells[order] < 20000]
+    picks = list(order[:6]) + list(rng.choice(small, 2, replace=False)) + [small[np.argmax(s[small])]]
+    print("patches", [(int(p), ps.n[p], int(s[p])) for p in picks], flush=True)
+    got = T.cpu().numpy()
+    for p in picks:
+        n = ps.n[p]
+        shape = (n[2], n[1], n[0])
+        Tp = T0[off[p]:off[p + 1]].cpu().numpy().reshape(shape)
+        bp = b[3 * off[p]:3 * off[p + 1]].double().cpu().numpy().reshape((3,) + shape)
+        g = oracle_grid(n, (1 / 64,) * 3, 3, ps.params)
+        To, s_ref, _ = oracle.superstep(g, Tp, bp, dts[p])
+        assert s_ref == s[p], p
+        err = rel_l1(got[off[p]:off[p + 1]].reshape(shape), To)
+        assert err <= 1e-5, (p, err)
+    plan.close()

@@ -162,8 +162,8 @@ def _window_t(torch, t, center, r):
 
 def test_fused_768_sampled_full_size(torch_cuda):
     """768^3 tangled field, kappa = T^2.5, kappa_perp = 1e-3, MC, saturation,
-    s = 32: one full-size super-step with every two-stage variant against
-    the oracle at sampled cells (periodic windows of half-width s+1, which
+    s = 32: one full-size super-step with every two-stage variant and the
+    one-stage 32x8 variants against the oracle at sampled cells (periodic windows of half-width s+1, which
     the stencil cannot cross in s stages)."""
     torch = torch_cuda
     from paper_1702_05487_amd import rkl
@@ -186,7 +186,7 @@ def test_fused_768_sampled_full_size(torch_cuda):
     print("oracle samples done", flush=True)
     idx = tuple(torch.tensor(np.array(centers).T, device="cuda:0"))
     t0 = T0[idx].cpu().numpy()
-    for v in FUSED:
+    for v in [0, 1] + list(FUSED):        # one-stage variants too: the autotuner may pick them
         plan.set_variant(v)
         T = T0.clone()
         assert plan.superstep(T, b, dt) == s_target

@@ -241,3 +241,48 @@ def test_spitzer_256_sampled_full_size(torch_cuda, precision, tol):
     T0 = w.T[tuple(np.array(centers).T)]
     assert np.abs(got - ref).max() <= tol * 4
     assert rel_l1(got - T0, ref - T0) <= (1e-9 if precision == "fp64" else 1e-2)
+
+
+def _window_t(torch, t, center, r):
+    """periodic window of half-width r of a [n2][n1][n0] (or (3, ...)) torch
+    tensor, copied to the host as float64"""
+    lead = t.dim() - 3
+    a = t
+    for ax, c in enumerate(center):
+        idx = torch.arange(c - r, c + r + 1, device=t.device) % t.shape[lead + ax]
+        a = a.index_select(lead + ax, idx)
+    return a.double().cpu().numpy()
+
+
+def test_saturated_512_sampled_full_size(torch_cuda):
+    """512^3 tangled field, kappa = T^2.5, kappa_perp = 1e-3, MC, saturation,
+    mixed precision, s = 24: one full-size super-step with the one-stage
+    variants (32x8 tiles, z-chunks 32 and 64) against the oracle at sampled
+    cells (periodic windows of half-width s+1)."""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    w = inputs.saturated_512(fields=False)
+    T0 = inputs.noisy_temperature(w.n, 2, device="cuda:0")
+    b = inputs.tangled_b(w.n, 1, device="cuda:0").float()
+    plan = rkl.Plan([lib_desc(w.n, w.h, 3, w.params)], precision="mixed")
+    dt = w.ratio * plan.dt_par(T0)
+    s_target = 24
+    rng = np.random.default_rng(13)
+    centers = [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(3)] + [(0, 511, 0), (511, 0, 511)]
+    r = s_target + 1
+    ref = []
+    for c in centers:
+        win = oracle.Grid(n=(2 * r + 1,) * 3, h=tuple(w.h), ndim=3, **w.params)
+        ref.append(oracle.rkl2_fixed(win, _window_t(torch, T0, c, r), _window_t(torch, b, c, r), s_target, dt)[r, r, r])
+    ref = np.array(ref)
+    idx = tuple(torch.tensor(np.array(centers).T, device="cuda:0"))
+    t0 = T0[idx].cpu().numpy()
+    for v in (0, 1):
+        plan.set_variant(v)
+        T = T0.clone()
+        assert plan.superstep(T, b, dt) == s_target
+        got = T[idx].cpu().numpy()
+        print("  variant %d: max |diff| %.3e" % (v, np.abs(got - ref).max()), flush=True)
+        assert np.abs(got - ref).max() <= 4e-5
+        assert rel_l1(got - t0, ref - t0) <= 1e-2
+    plan.close()
