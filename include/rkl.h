@@ -91,11 +91,14 @@ typedef struct {
 
 /*
  * rkl_plan: validate `ngrids` grid descriptors and allocate the plan's device
- * scratch (two FP64 stage buffers, the tau*M(Y0) buffer, reduction space and
- * the RKL2 coefficient table for s = 2..smax, Appendix A).  Grids are packed
- * back to back for the batched entry points; rkl_grid_offset gives each
- * grid's first cell.  The device current at this call is the plan's device.
- * Errors: RKL_EINVAL for a bad descriptor, RKL_ENOMEM, RKL_EDEVICE.
+ * scratch (two FP64 stage buffers -- four if opt->variant is a two-stage
+ * variant --, the tau*M(Y0) buffer, reduction space and the RKL2 coefficient
+ * table for s = 2..smax, Appendix A).  Grids are packed back to back for the
+ * batched entry points; rkl_grid_offset gives each grid's first cell.  The
+ * device current at this call is the plan's device.  opt may be NULL
+ * (RKL_FP64, default variant, default smax).
+ * Errors: RKL_EINVAL for a bad descriptor or option (including a two-stage
+ * variant for a plan that cannot use it), RKL_ENOMEM, RKL_EDEVICE.
  */
 rkl_status rkl_plan(const rkl_grid_desc *grids, int32_t ngrids, const rkl_options *opt,
                     rkl_plan_t *plan_out);

@@ -378,9 +378,16 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
     int j = 2;
     while (j <= S) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
+        size_t rec = 0;
         if (p->prof) {
+            // owned by the plan from here on (prof_clear destroys them)
             HIPCHECK(hipEventCreate(&e0), "event create");
-            HIPCHECK(hipEventCreate(&e1), "event create");
+            if (hipEventCreate(&e1) != hipSuccess) {
+                hipEventDestroy(e0);
+                return fail(RKL_EDEVICE, "event create");
+            }
+            rec = p->prof_recs.size();
+            p->prof_recs.push_back({e0, e1, 0, 0});
             HIPCHECK(hipEventRecord(e0, s), "event record");
         }
         int done;
@@ -404,7 +411,8 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
         }
         if (p->prof) {
             HIPCHECK(hipEventRecord(e1, s), "event record");
-            p->prof_recs.push_back({e0, e1, done, done * n});
+            p->prof_recs[rec].fuse = done;
+            p->prof_recs[rec].cells = done * n;
         }
         j += done;
     }
