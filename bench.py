@@ -147,9 +147,10 @@ def copy_ceiling(torch):
 def bench_batched(args, torch, inputs, rkl):
     """2000 independent periodic patches (edges log-uniform in [16, 64], own
     fields, dt_hyp for s_p uniform in [4, 40]), one super-step of all of them
-    per step: the captured HIP graph of rkl_superstep_batched replayed.  The
-    roofline comes from the same launches run eagerly right after the timed
-    replays, each stage launch of j >= 2 timed with HIP events."""
+    per step: the captured HIP graph of rkl_superstep_batched replayed, with
+    the batched tile policy picked by the autotuner first.  The roofline
+    comes from the same launches run eagerly right after the timed replays,
+    each stage launch of j >= 2 timed with HIP events."""
     import numpy as np
     ps = inputs.patch_set(2000, device="cuda:0")
     descs = [rkl.grid_desc(n, (1 / 64,) * 3, ndim=3, **ps.params) for n in ps.n]
@@ -163,6 +164,7 @@ def bench_batched(args, torch, inputs, rkl):
     dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
     s_out = torch.zeros(len(descs), dtype=torch.int32, device="cuda:0")
     s_acc = torch.zeros(len(descs), dtype=torch.int64, device="cuda:0")
+    policy, tuned_ms = plan.autotune_batched(T0, b, dt, reps=2)   # tile policy by timed search
     T = T0.clone()
     plan.graph_capture(T, b, dt, s_out)
     for _ in range(args.warmup):
@@ -210,6 +212,8 @@ def bench_batched(args, torch, inputs, rkl):
             "stages_min": int(s1.min()), "stages_max": int(s1.max()), "precision": "mixed",
             "kappa_par": "T^2.5", "kperp_ratio": ps.params["kperp_ratio"], "limiter": "MC",
             "saturation": False, "launch": "hipGraph replay, one launch per stage", "flags": int(flags),
+            "tile_policy": policy, "policy_half_rows_tile_z": list(rkl.rkl_batch_policy_info(policy)),
+            "autotuned_ms_per_step": tuned_ms,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -221,25 +225,38 @@ def bench_batched(args, torch, inputs, rkl):
     }
 
 
-def cpu_baseline(w, T0, b, s, dt):
+def cpu_baseline(w, T0, b, dt, precision, torch, rkl):
     """The oracle, untuned, on a bounded sample of the same workload: one
-    super-step (s stages) of a 256 x 256 x 16 periodic slab cut from the same
-    fields (host arrays T0 [16][256][256], b [3][16][256][256]), on one host
-    core."""
+    super-step of length dt of a 256 x 256 x 16 periodic slab cut from the
+    same fields (host arrays T0 [16][256][256], b [3][16][256][256]), on one
+    host core.  The library then runs the same slab (as its own periodic
+    grid, in the plan's precision) and its error against the oracle is
+    returned with the baseline."""
     import numpy as np
     import oracle
-    nz = 16
-    m = 256
+    nz, m = 16, 256
     T = np.ascontiguousarray(T0)
     b = np.ascontiguousarray(b)
     g = oracle.Grid(n=(m, m, nz), h=w.h, ndim=3, **w.params)
     t0 = time.perf_counter()
-    oracle.rkl2_fixed(g, T, b, s, dt)
+    ref, s, _ = oracle.superstep(g, T, b, dt)
     sec = time.perf_counter() - t0
     cells = m * m * nz
-    return {"value": cells * s / sec, "unit": "cell-stage/s", "cores": 1, "kind": "oracle",
+    base = {"value": cells * s / sec, "unit": "cell-stage/s", "cores": 1, "kind": "oracle",
             "sample": "one %d-stage super-step of a %dx%dx%d periodic slab cut from the same fields "
                       "(%.1f s serial)" % (s, m, m, nz, sec)}
+    plan = rkl.Plan([rkl.grid_desc((m, m, nz), w.h, ndim=3, **w.params)], precision=precision)
+    Td = torch.from_numpy(T).to("cuda:0")
+    bd = torch.from_numpy(b).to("cuda:0", dtype=torch.float32 if precision == "mixed" else torch.float64)
+    s_gpu = plan.superstep(Td, bd, dt)
+    got = Td.cpu().numpy()
+    plan.close()
+    acc = {"rel_l1": float(np.abs(got - ref).sum() / np.abs(ref).sum()),
+           "linf": float(np.abs(got - ref).max()),
+           "rel_l1_change": float(np.abs(got - ref).sum() / np.abs(ref - T).sum()),
+           "stages": [int(s_gpu), int(s)],
+           "sample": "the same slab and super-step, library (%s) vs oracle (FP64)" % precision}
+    return base, acc
 
 
 def main():
@@ -360,7 +377,7 @@ def main():
     out["roofline"]["copy_GBs"] = ceil
     out["roofline"]["frac_of_copy"] = achieved / ceil
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, T0_host, b_host, s_last, dt)
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline(w, T0_host, b_host, dt, precision, torch, rkl)
     print(json.dumps(out), flush=True)
 
 

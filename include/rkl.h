@@ -218,6 +218,25 @@ rkl_status rkl_profile_read(rkl_plan_t plan, int32_t fuse, double *ms, int64_t *
 rkl_status rkl_autotune(rkl_plan_t plan, int32_t grid, const double *T, const void *b, double dt_hyp,
                         int32_t reps, int32_t *best_variant, double *best_ms, void *stream);
 
+/*
+ * Tile policies of the batched launch: rkl_batch_policy_count() of them.
+ * rkl_batch_policy_info gives a policy's z-chunk length (tile_z planes) and
+ * whether grids wider than 32 cells are split into half-width rows
+ * (half_rows 1) instead of full-width ones (any pointer may be NULL).
+ * rkl_set_batch_policy selects one for a plan (policy 0 by default); a graph
+ * captured before is dropped (rkl_graph_launch then returns RKL_ESTATE until
+ * the next capture).  rkl_autotune_batched times `reps` batched super-steps
+ * with every policy on a plan-owned scratch copy of the packed T (T itself
+ * is not modified; dt_hyp is the device array of ngrids doubles), selects
+ * the fastest and returns its index and average super-step time.  It
+ * allocates the scratch for the duration of the call and synchronises.
+ */
+int32_t rkl_batch_policy_count(void);
+rkl_status rkl_batch_policy_info(int32_t policy, int32_t *half_rows, int32_t *tile_z);
+rkl_status rkl_set_batch_policy(rkl_plan_t plan, int32_t policy);
+rkl_status rkl_autotune_batched(rkl_plan_t plan, const double *T, const void *b, const double *dt_hyp,
+                                int32_t reps, int32_t *best_policy, double *best_ms, void *stream);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *rkl_last_error(void);
 

@@ -49,6 +49,7 @@ struct rkl_plan_s {
     int32_t* s_dev = nullptr;   // scratch for the stage-count read-back
     int32_t* s_host = nullptr;  // pinned
     BatchPlan* batch = nullptr; // batched launch data (rkl_batch.hip)
+    int batch_policy = 0;       // its tile policy
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     // kernel timing (rkl_profile): one event pair per stencil launch of
@@ -166,9 +167,97 @@ static void free_plan(rkl_plan_s* p) {
     delete p;
 }
 
+static rkl_status ensure_batch(rkl_plan_s* p) {
+    if (p->batch) return RKL_OK;
+    std::string why;
+    rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, p->batch_policy, &p->batch, why);
+    return st == RKL_OK ? RKL_OK : fail(st, why);
+}
+
+// Replace the batched launch data by that of `policy`; a captured graph
+// refers to the old data, so it is dropped.
+static rkl_status select_batch_policy(rkl_plan_s* p, int policy) {
+    if (p->batch && policy == p->batch_policy) return RKL_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hipfail(e, "policy sync");
+    if (p->graph_exec) { hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+    batch_free(p->batch);
+    p->batch = nullptr;
+    p->batch_policy = policy;
+    return ensure_batch(p);
+}
+
 extern "C" {
 
 const char* rkl_last_error(void) { return g_err.c_str(); }
+
+int32_t rkl_batch_policy_count(void) { return batch_policy_count(); }
+
+rkl_status rkl_batch_policy_info(int32_t policy, int32_t* half_rows, int32_t* tile_z) {
+    if (policy < 0 || policy >= batch_policy_count()) return fail(RKL_EINVAL, "policy out of range");
+    int h = 0, z = 0;
+    batch_policy_info(policy, &h, &z);
+    if (half_rows) *half_rows = h;
+    if (tile_z) *tile_z = z;
+    return RKL_OK;
+}
+
+rkl_status rkl_set_batch_policy(rkl_plan_t p, int32_t policy) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (policy < 0 || policy >= batch_policy_count()) return fail(RKL_EINVAL, "policy out of range");
+    return select_batch_policy(p, policy);
+}
+
+rkl_status rkl_autotune_batched(rkl_plan_t p, const double* T, const void* b, const double* dt_hyp,
+                                int32_t reps, int32_t* best_policy, double* best_ms, void* stream) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
+    if (reps < 1 || reps > 1000) return fail(RKL_EINVAL, "reps must be in [1, 1000]");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = sizeof(double) * (size_t)p->total;
+    double* W = nullptr;
+    HIPCHECK(hipMalloc(&W, bytes), "autotune scratch");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool saved_prof = p->prof;
+    const int saved = p->batch_policy;
+    p->prof = false;
+    int best = -1;
+    float best_t = 0.f;
+    rkl_status res = RKL_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) res = fail(RKL_EDEVICE, "autotune events");
+    for (int pol = 0; res == RKL_OK && pol < batch_policy_count(); ++pol) {
+        res = select_batch_policy(p, pol);
+        if (res != RKL_OK) break;
+        BatchBuffers bb{W, b, dt_hyp, nullptr, p->Ya, p->Yb, p->MY0, p->coef, p->state};
+        // one untimed super-step from the caller's T, then reps timed ones
+        hipError_t e = hipMemcpyAsync(W, T, bytes, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = batch_launch(p->batch, bb, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(W, T, bytes, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int r = 0; e == hipSuccess && r < reps; ++r) e = batch_launch(p->batch, bb, s);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) { res = hipfail(e, "batched autotune"); break; }
+        if (best < 0 || t < best_t) { best = pol; best_t = t; }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipStreamSynchronize(s);
+    hipFree(W);
+    p->prof = saved_prof;
+    if (res != RKL_OK) {
+        select_batch_policy(p, saved);
+        return res;
+    }
+    res = select_batch_policy(p, best);
+    if (res != RKL_OK) return res;
+    if (best_policy) *best_policy = best;
+    if (best_ms) *best_ms = best_t / reps;
+    return RKL_OK;
+}
 
 int32_t rkl_variant_count(void) { return variant_count(); }
 
@@ -262,7 +351,7 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
     if (e != hipSuccess) { free_plan(p); return hipfail(e, "plan upload"); }
     if (ngrids > 1) {
         std::string why;
-        rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, &p->batch, why);
+        rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, 0, &p->batch, why);
         if (st != RKL_OK) { free_plan(p); return fail(st, why); }
     }
     if (o.variant > 0) {
@@ -515,11 +604,8 @@ rkl_status rkl_superstep_batched(rkl_plan_t p, double* T, const void* b, const d
                                  void* stream) {
     if (!p) return fail(RKL_EINVAL, "plan is NULL");
     if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
-    if (!p->batch) {
-        std::string why;
-        rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, &p->batch, why);
-        if (st != RKL_OK) return fail(st, why);
-    }
+    rkl_status st = ensure_batch(p);
+    if (st != RKL_OK) return st;
     BatchBuffers bb{T, b, dt_hyp, s_out, p->Ya, p->Yb, p->MY0, p->coef, p->state};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     hipError_t e = batch_launch(p->batch, bb, (hipStream_t)stream, p->prof ? &ev : nullptr);
@@ -534,11 +620,8 @@ rkl_status rkl_graph_capture(rkl_plan_t p, double* T, const void* b, const doubl
                              void* stream) {
     if (!p) return fail(RKL_EINVAL, "plan is NULL");
     if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
-    if (!p->batch) {
-        std::string why;
-        rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, &p->batch, why);
-        if (st != RKL_OK) return fail(st, why);
-    }
+    rkl_status st = ensure_batch(p);
+    if (st != RKL_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     hipStream_t cap;
     HIPCHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");

@@ -23,9 +23,12 @@ struct BatchBuffers {
     GridState* state;      // ngrids
 };
 
+// policy: index into the batched tile policies (batch_policy_count())
 rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vector<GridConst>& gc,
-                        const std::vector<int64_t>& off, int precision, int smax, BatchPlan** out,
-                        std::string& why);
+                        const std::vector<int64_t>& off, int precision, int smax, int policy,
+                        BatchPlan** out, std::string& why);
+int batch_policy_count();
+void batch_policy_info(int policy, int* half_rows, int* bz);
 void batch_free(BatchPlan* bp);
 // Enqueue one super-step of every grid (no host synchronisation).  With
 // `events` non-NULL, a pair of HIP events (created here, owned by the caller)

@@ -162,16 +162,39 @@ __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int
 // tile shape for one grid: full-width rows when the grid is at most 64 cells
 // wide, as many rows as fit 256 threads (at most 64), the whole z extent up
 // to 32 planes per tile
-static void choose_tile(const GridConst& g, int& bx, int& by, int& bz) {
+// Tile policies of the batched launch: z-chunk length and row width.  Rows
+// are the grid's full width (up to 64 cells), or half of it for grids wider
+// than 32 cells (twice the tiles, shorter halo rows); by fills the 256
+// threads.
+struct BatchPolicy {
+    int half_rows;
+    int bz;
+};
+static const BatchPolicy kPolicies[] = {{0, 32}, {0, 16}, {0, 64}, {1, 32}, {1, 16}, {1, 64}};
+
+int batch_policy_count() { return (int)(sizeof(kPolicies) / sizeof(kPolicies[0])); }
+
+void batch_policy_info(int policy, int* half_rows, int* bz) {
+    *half_rows = kPolicies[policy].half_rows;
+    *bz = kPolicies[policy].bz;
+}
+
+static void choose_tile(const GridConst& g, int policy, int& bx, int& by, int& bz) {
+    const BatchPolicy& P = kPolicies[policy];
     bx = std::min(g.n0, 64);
+    if (P.half_rows && g.n0 > 32) bx = std::min((g.n0 + 1) / 2, 32);
     by = std::min(std::min(g.n1, kBT / bx), 64);
-    bz = std::min(g.n2, 32);
+    bz = std::min(g.n2, P.bz);
 }
 
 rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vector<GridConst>& gc,
-                        const std::vector<int64_t>& off, int precision, int smax, BatchPlan** out,
-                        std::string& why) {
+                        const std::vector<int64_t>& off, int precision, int smax, int policy,
+                        BatchPlan** out, std::string& why) {
     *out = nullptr;
+    if (policy < 0 || policy >= batch_policy_count()) {
+        why = "batched tile policy out of range";
+        return RKL_EINVAL;
+    }
     const int n = (int)desc.size();
     std::vector<BatchGrid> h(n);
     int64_t items = 0;
@@ -185,7 +208,7 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
         BatchGrid& B = h[g];
         B.gc = gc[g];
         B.off = off[g];
-        choose_tile(gc[g], B.bx, B.by, B.bz);
+        choose_tile(gc[g], policy, B.bx, B.by, B.bz);
         if ((B.bx + 2) * (B.by + 2) > kPL || (B.bx + 1) * B.by > kFX || B.bx * (B.by + 1) > kFY ||
             2 * B.bx + 2 * B.by + 4 > kBT) {
             why = "internal: batched tile shape exceeds the LDS layout";

@@ -25,6 +25,7 @@ EXPORTS = [
     "rkl_superstep", "rkl_superstep_batched", "rkl_graph_capture", "rkl_graph_launch",
     "rkl_query", "rkl_variant_count", "rkl_variant_info", "rkl_set_variant", "rkl_last_error",
     "rkl_profile", "rkl_profile_read", "rkl_autotune",
+    "rkl_batch_policy_count", "rkl_batch_policy_info", "rkl_set_batch_policy", "rkl_autotune_batched",
 ]
 
 
@@ -94,6 +95,10 @@ def load(build_if_missing: bool = True):
         "rkl_profile": (i32, [vp, i32]),
         "rkl_profile_read": (i32, [vp, i32, P(dbl), P(i64), P(i64)]),
         "rkl_autotune": (i32, [vp, i32, vp, vp, dbl, i32, P(i32), P(dbl), vp]),
+        "rkl_batch_policy_count": (i32, []),
+        "rkl_batch_policy_info": (i32, [i32, P(i32), P(i32)]),
+        "rkl_set_batch_policy": (i32, [vp, i32]),
+        "rkl_autotune_batched": (i32, [vp, vp, vp, vp, i32, P(i32), P(dbl), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -182,6 +187,28 @@ def rkl_autotune(plan, grid, T_ptr, b_ptr, dt_hyp, reps, stream):
     v, ms = ctypes.c_int32(), ctypes.c_double()
     _check(load().rkl_autotune(plan, grid, T_ptr, b_ptr, float(dt_hyp), int(reps), ctypes.byref(v),
                                ctypes.byref(ms), stream))
+    return v.value, ms.value
+
+
+def rkl_batch_policy_count():
+    return load().rkl_batch_policy_count()
+
+
+def rkl_batch_policy_info(policy):
+    """(half_rows, tile_z) of a batched tile policy."""
+    h, z = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().rkl_batch_policy_info(policy, ctypes.byref(h), ctypes.byref(z)))
+    return h.value, z.value
+
+
+def rkl_set_batch_policy(plan, policy):
+    _check(load().rkl_set_batch_policy(plan, policy))
+
+
+def rkl_autotune_batched(plan, T_ptr, b_ptr, dt_ptr, reps, stream):
+    v, ms = ctypes.c_int32(), ctypes.c_double()
+    _check(load().rkl_autotune_batched(plan, T_ptr, b_ptr, dt_ptr, int(reps), ctypes.byref(v),
+                                       ctypes.byref(ms), stream))
     return v.value, ms.value
 
 
@@ -307,3 +334,14 @@ class Plan:
 
     def graph_launch(self):
         rkl_graph_launch(self.handle, _stream())
+
+    def set_batch_policy(self, policy):
+        rkl_set_batch_policy(self.handle, policy)
+
+    def autotune_batched(self, T, b, dt_hyp, reps=2):
+        """Pick the fastest batched tile policy by timing; returns (policy, ms)."""
+        import torch
+        tot = sum(self.cells)
+        return rkl_autotune_batched(self.handle, _dev_ptr(T, torch.float64, tot, "T"),
+                                    _dev_ptr(b, self.bdtype, 3 * tot, "b"),
+                                    _dev_ptr(dt_hyp, torch.float64, len(self.descs), "dt_hyp"), reps, _stream())

@@ -83,3 +83,16 @@ def test_variant_table():
     assert fuses == {1, 2}
     with pytest.raises(rkl.RklError):
         rkl.rkl_variant_info(n)
+
+
+def test_batch_policy_table():
+    n = rkl.rkl_batch_policy_count()
+    assert n >= 2
+    seen = set()
+    for p in range(n):
+        half, tz = rkl.rkl_batch_policy_info(p)
+        assert half in (0, 1) and tz >= 1
+        seen.add((half, tz))
+    assert len(seen) == n           # no duplicate policies
+    with pytest.raises(rkl.RklError):
+        rkl.rkl_batch_policy_info(n)

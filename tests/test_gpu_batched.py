@@ -199,3 +199,67 @@ def test_patches_2000_full_size_sampled(torch_cuda):
         err = rel_l1(got[off[p]:off[p + 1]].reshape(shape), To)
         assert err <= 1e-5, (p, err)
     plan.close()
+
+
+def test_every_batch_policy_gives_the_same_bits(torch_cuda):
+    """Tiling changes which workgroup computes a face, never the operations,
+    so every batched tile policy gives the same bits."""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    ps = small_patch_set(16, seed=9, lo=8, hi=60)
+    _, _, dts = oracle_patches(ps, "mixed")
+    plan = make_plan(ps, "mixed")
+    T, b = pack(torch, ps, "mixed")
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
+    ref = None
+    for pol in range(rkl.rkl_batch_policy_count()):
+        plan.set_batch_policy(pol)
+        Tp = T.clone()
+        plan.superstep_batched(Tp, b, dt)
+        if ref is None:
+            ref = Tp
+        else:
+            assert torch.equal(Tp, ref), pol
+    plan.close()
+
+
+def test_policy_change_drops_the_graph(torch_cuda):
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    ps = small_patch_set(6, seed=10)
+    _, _, dts = oracle_patches(ps, "fp64")
+    plan = make_plan(ps, "fp64")
+    T, b = pack(torch, ps, "fp64")
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
+    plan.graph_capture(T, b, dt)
+    plan.graph_launch()
+    plan.set_batch_policy(1)
+    with pytest.raises(rkl.RklError) as e:
+        plan.graph_launch()
+    assert e.value.status == rkl.RKL_ESTATE
+    plan.graph_capture(T, b, dt)
+    plan.graph_launch()
+    torch.cuda.synchronize()
+    plan.close()
+
+
+def test_batched_autotune(torch_cuda):
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    ps = small_patch_set(12, seed=11, lo=8, hi=48)
+    ref, sref, dts = oracle_patches(ps, "mixed")
+    plan = make_plan(ps, "mixed")
+    T, b = pack(torch, ps, "mixed")
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
+    T_before = T.clone()
+    pol, ms = plan.autotune_batched(T, b, dt, reps=1)
+    assert torch.equal(T, T_before)              # the caller's T is not touched
+    assert 0 <= pol < rkl.rkl_batch_policy_count() and ms > 0
+    plan.superstep_batched(T, b, dt)
+    got = T.cpu().numpy()
+    off = plan.offsets()
+    for p in range(len(ps.n)):
+        assert rel_l1(got[off[p]:off[p + 1]].reshape(ref[p].shape), ref[p]) <= 1e-5, p
+    with pytest.raises(rkl.RklError):
+        plan.autotune_batched(T, b, dt, reps=0)
+    plan.close()
