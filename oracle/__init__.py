@@ -4,5 +4,5 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
 CPU-baseline leg may use this package; the product path never does.
 """
 from .oracle import (  # noqa: F401
-    Grid, build, load, mc, stages, coeffs, dt_par, flux_div, rkl2_fixed, superstep,
+    Grid, build, load, mc, stages, coeffs, dt_par, flux_div, rkl2_fixed, superstep, subcycle,
 )

@@ -108,6 +108,8 @@ def load():
         lib.orc_rkl2_fixed.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double]
         lib.orc_rkl2_fixed.restype = None
         lib.orc_superstep.argtypes = [gp, dp, dp, ctypes.c_double, dp]
+        lib.orc_subcycle.argtypes = [gp, dp, dp, ctypes.c_double, ctypes.c_long]
+        lib.orc_subcycle.restype = ctypes.c_long
         lib.orc_superstep.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -179,3 +181,12 @@ def superstep(g: Grid, T, b, dt_hyp: float):
     dtp = ctypes.c_double()
     s = load().orc_superstep(ctypes.byref(cg), _ptr(T), _ptr(b), float(dt_hyp), ctypes.byref(dtp))
     return T, s, dtp.value
+
+
+def subcycle(g: Grid, T, b, dt_hyp: float, max_sub: int = 1 << 20):
+    """Explicit sub-cycling over dt_hyp; returns (T_new, n_sub)."""
+    T = _field(g, T, "T").copy()
+    b = _bfield(g, b)
+    cg = g.c()
+    n = load().orc_subcycle(ctypes.byref(cg), _ptr(T), _ptr(b), float(dt_hyp), int(max_sub))
+    return T, n

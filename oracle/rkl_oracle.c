@@ -297,3 +297,27 @@ int orc_superstep(const orc_grid *g, double *T, const double *b, double dt_hyp, 
     orc_rkl2_fixed(g, T, b, s, dt_hyp);
     return s;
 }
+
+/* Sub-cycling (Sec. 2.3, explicit methods; Sec. 5.2 case (b)): the conduction
+ * operator applied N_sub times with a stable step, here
+ * N_sub = ceil(dt_hyp / dt_par) with dt_par of Eq. dt_exp taken from T at the
+ * start, each sub-step forward Euler  T <- T + tau (gamma-1)/rho (-div F_c(T))
+ * with tau = dt_hyp / N_sub <= dt_par.  Returns N_sub (0 when dt_hyp = 0 or
+ * there is no conduction: T unchanged; -1 if N_sub would exceed max_sub). */
+long orc_subcycle(const orc_grid *g, double *T, const double *b, double dt_hyp, long max_sub)
+{
+    const double dtp = orc_dt_par(g, T);
+    if (!(dt_hyp > 0.0) || isinf(dtp)) return 0;
+    const double q = ceil(dt_hyp / dtp);
+    if (!(q <= (double)max_sub)) return -1;
+    const long nsub = (long)q;
+    const double tau = dt_hyp / (double)nsub;
+    const long N = ncell(g);
+    double *L = malloc(sizeof(double) * N);
+    for (long k = 0; k < nsub; ++k) {
+        orc_flux_div(g, T, b, L);
+        for (long i = 0; i < N; ++i) T[i] = T[i] + tau * L[i];
+    }
+    free(L);
+    return nsub;
+}
