@@ -32,6 +32,7 @@ WORKLOADS = {
     "saturated_512_fp64": ("saturated_512", "fp64"),
     "fused_768": ("fused_768", "mixed"),
     "patches_2000": ("patch_set", "mixed"),   # batched, graph-captured
+    "spitzer_256_subcycle": ("spitzer_256", "fp64"),   # explicit sub-cycling over the same dt_hyp
 }
 KERNEL_SOURCES = {
     1: ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_kernels.hip"],
@@ -225,6 +226,82 @@ def bench_batched(args, torch, inputs, rkl):
     }
 
 
+def bench_subcycle(args, torch, inputs, rkl):
+    """Explicit sub-cycling (N_sub = ceil(dt_hyp/dt_par) forward-Euler
+    sub-steps) of the 256^3 FP64 workload over the dt_hyp that gives its
+    RKL2 super-step s = 16, against that super-step on the same fields: the
+    measured speed-up of super-time-stepping over sub-cycling on this GPU.
+    One step = one dt_hyp interval; value = cell-sub-steps per second."""
+    dev = torch.device("cuda:0")
+    w = inputs.spitzer_256(device=dev)
+    plan = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision="fp64")
+    T0, w.T = w.T, None
+    b, w.b = w.b, None
+    T = T0.clone()
+    dt = w.ratio * plan.dt_par(T)
+    if args.variant >= 0:
+        plan.set_variant(args.variant)
+    else:
+        rkl.rkl_autotune(plan.handle, 0, *plan._tb(0, T, b), dt, 2,
+                         rkl.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 1)):
+            T.copy_(T0)
+            fn()
+        total, count = 0.0, 0
+        for _ in range(args.steps):
+            T.copy_(T0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            count += fn()
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+        return total, count
+
+    sec_sts, stages = timed(lambda: plan.superstep(T, b, dt))
+    rkl.rkl_profile(plan.handle, 1)
+    sec_sub, nsub = timed(lambda: plan.subcycle(T, b, dt))
+    ms, launches, _ = rkl.rkl_profile_read(plan.handle, 3)
+    rkl.rkl_profile(plan.handle, 0)
+    plan.close()
+    cells = w.cells
+    bpc = 40.0                                   # read Y 8 + b 24, write 8
+    achieved = bpc * cells / (ms / 1e3 / launches) / 1e9
+    del T, T0, b
+    torch.cuda.empty_cache()
+    ceil = copy_ceiling(torch)
+    return {
+        "metric": "cell-stage updates/s",
+        "value": cells * nsub / sec_sub,
+        "unit": "cell-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_sub * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "tangled3d_256_fp64 explicit sub-cycling", "grid": list(w.n),
+            "substeps_per_step": nsub // args.steps, "precision": "fp64", "kappa_par": "T^2.5",
+            "kperp_ratio": w.params["kperp_ratio"], "limiter": "MC", "saturation": False,
+            "rkl2_stages_same_dt": stages // args.steps,
+            "rkl2_ms_per_step": sec_sts * 1e3 / args.steps,
+            "sts_speedup": sec_sub / sec_sts,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "kernel": "stage_kernel (explicit sub-steps)", "bytes_per_cell_stage": bpc,
+            "avg_launch_ms": ms / launches, "launches": launches,
+            "copy_GBs": ceil, "frac_of_copy": achieved / ceil,
+        },
+    }
+
+
 def cpu_baseline(w, T0, b, dt, precision, torch, rkl):
     """The oracle, untuned, on a bounded sample of the same workload: one
     super-step of length dt of a 256 x 256 x 16 periodic slab cut from the
@@ -292,6 +369,9 @@ def main():
     rkl.load(build_if_missing=True)
     if args.workload == "patches_2000":
         print(json.dumps(bench_batched(args, torch, inputs, rkl)), flush=True)
+        return
+    if args.workload == "spitzer_256_subcycle":
+        print(json.dumps(bench_subcycle(args, torch, inputs, rkl)), flush=True)
         return
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")

@@ -144,6 +144,21 @@ rkl_status rkl_superstep(rkl_plan_t plan, int32_t grid, double *T, const void *b
                          double dt_hyp, int32_t *s_out, void *stream);
 
 /*
+ * rkl_subcycle: explicit sub-cycling of the conduction operator over dt_hyp
+ * on one grid, T updated in place (Sec. 2.3, the sub-cycled alternative the
+ * paper compares super-time-stepping with): N_sub = ceil(dt_hyp / dt_par)
+ * forward-Euler sub-steps T <- T + tau (gamma-1)/rho (-div F_c(T)) with
+ * tau = dt_hyp / N_sub <= dt_par, dt_par of Eq. dt_exp taken from T at the
+ * start.  Reads dt_par back once (one synchronisation of `stream`); stores
+ * N_sub in *nsub_out (host pointer, may be NULL; 0 when dt_hyp = 0 or there
+ * is no conduction, T then unchanged).  RKL_ESTAGES (T unchanged) if N_sub
+ * would exceed max_sub.  Uses one plan stage buffer as the other half of a
+ * ping-pong; an odd N_sub ends with one device copy into T.
+ */
+rkl_status rkl_subcycle(rkl_plan_t plan, int32_t grid, double *T, const void *b, double dt_hyp,
+                        int64_t max_sub, int64_t *nsub_out, void *stream);
+
+/*
  * rkl_superstep_batched: one super-step of every grid of the plan at once
  * with no host synchronisation -- safe to capture in a HIP graph: one
  * reduce launch (dt_par and s per grid on the device), then one launch per
@@ -197,11 +212,12 @@ rkl_status rkl_set_variant(rkl_plan_t plan, int32_t variant);
  * Kernel timing for benchmarks.  rkl_profile(plan, 1) starts recording, with
  * a pair of HIP events on the caller's stream around each stencil launch of
  * stages j >= 2 of every following rkl_superstep and (eager, not captured)
- * rkl_superstep_batched (the dominant kernels); rkl_profile(plan, 0) stops
- * and discards.  rkl_profile_read synchronises and returns, over the
- * launches with `fuse` stages each (1 or 2), the summed duration in ms, the
- * number of launches and of cell-stage updates (batched launches count 0
- * cell-stages: their work follows from the device-side stage counts).
+ * rkl_superstep_batched (the dominant kernels) and around each sub-step
+ * launch of rkl_subcycle; rkl_profile(plan, 0) stops and discards.
+ * rkl_profile_read synchronises and returns, over the launches of one kind
+ * -- `fuse` 1: one-stage, 2: two-stage, 3: sub-cycling -- the summed
+ * duration in ms, the number of launches and of cell updates (batched
+ * launches count 0: their work follows from the device-side stage counts).
  */
 rkl_status rkl_profile(rkl_plan_t plan, int32_t enable);
 rkl_status rkl_profile_read(rkl_plan_t plan, int32_t fuse, double *ms, int64_t *launches,

@@ -508,6 +508,62 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
     return RKL_OK;
 }
 
+rkl_status rkl_subcycle(rkl_plan_t p, int32_t g, double* T, const void* b, double dt_hyp, int64_t max_sub,
+                        int64_t* nsub_out, void* stream) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    if (nsub_out) *nsub_out = 0;
+    if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
+    if (max_sub < 1) return fail(RKL_EINVAL, "max_sub must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    st = reduce_and_finalize(p, g, T, 0.0, 1, nullptr, s);
+    if (st != RKL_OK) return st;
+    double dtp = 0.0;
+    HIPCHECK(hipMemcpyAsync(&dtp, &p->state[g].dt_par, sizeof(double), hipMemcpyDeviceToHost, s), "dt_par copy");
+    HIPCHECK(hipStreamSynchronize(s), "dt_par sync");
+    if (dt_hyp == 0.0 || std::isinf(dtp)) return RKL_OK;   // nothing to do
+    // N_sub = ceil(dt_hyp / dt_par) forward-Euler sub-steps of dt_hyp / N_sub
+    const double q = std::ceil(dt_hyp / dtp);
+    if (!(q <= (double)max_sub))
+        return fail(RKL_ESTAGES, "sub-step count above max_sub (T unchanged)");
+    const int64_t nsub = (int64_t)q;
+    const double sub_scale = -(dt_hyp / (double)nsub) * p->gc[g].fac;
+    const GridConst& gc = p->gc[g];
+    const Variant v = variant_get(p->variant);
+    const int64_t n = p->off[g + 1] - p->off[g];
+    double* A = p->Ya + p->off[g];
+    for (int64_t k = 0; k < nsub; ++k) {
+        // T -> A -> T -> ...; an odd count leaves the result in A
+        const double* in = (k % 2 == 0) ? T : A;
+        double* out = (k % 2 == 0) ? A : T;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        size_t rec = 0;
+        if (p->prof) {
+            HIPCHECK(hipEventCreate(&e0), "event create");
+            if (hipEventCreate(&e1) != hipSuccess) {
+                hipEventDestroy(e0);
+                return fail(RKL_EDEVICE, "event create");
+            }
+            rec = p->prof_recs.size();
+            p->prof_recs.push_back({e0, e1, 0, 0});
+            HIPCHECK(hipEventRecord(e0, s), "event record");
+        }
+        HIPCHECK(launch_stage(p->precision, v, gc, 3, 0, in, nullptr, nullptr, nullptr, nullptr, out, b,
+                              p->state + g, p->coef, s, sub_scale),
+                 "sub-step launch");
+        if (p->prof) {
+            HIPCHECK(hipEventRecord(e1, s), "event record");
+            p->prof_recs[rec].fuse = 3;
+            p->prof_recs[rec].cells = n;
+        }
+    }
+    if (nsub % 2 == 1)
+        HIPCHECK(hipMemcpyAsync(T, A, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "result copy");
+    if (nsub_out) *nsub_out = nsub;
+    return RKL_OK;
+}
+
 rkl_status rkl_autotune(rkl_plan_t p, int32_t g, const double* T, const void* b, double dt_hyp, int32_t reps,
                         int32_t* best_variant, double* best_ms, void* stream) {
     rkl_status st = check_grid(p, g);
@@ -570,7 +626,7 @@ rkl_status rkl_profile(rkl_plan_t p, int32_t enable) {
 
 rkl_status rkl_profile_read(rkl_plan_t p, int32_t fuse, double* ms, int64_t* launches, int64_t* cells) {
     if (!p) return fail(RKL_EINVAL, "plan is NULL");
-    if (fuse != 1 && fuse != 2) return fail(RKL_EINVAL, "fuse must be 1 or 2");
+    if (fuse < 1 || fuse > 3) return fail(RKL_EINVAL, "fuse must be 1, 2 or 3");
     double tot = 0.0;
     int64_t nl = 0, nc = 0;
     for (const auto& r : p->prof_recs) {

@@ -84,11 +84,12 @@ hipError_t launch_reduce(const double* T, int64_t N, double* partials, int nbloc
 int reduce_blocks(int64_t N);
 hipError_t launch_finalize(const double* partials, int nblocks, const GridConst& gc, double dt_hyp,
                            int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st);
-// kind: 0 flux divergence into Yout, 1 first stage, 2 stage j >= 2
+// kind: 0 flux divergence into Yout, 1 first stage, 2 stage j >= 2,
+// 3 explicit sub-step Yout = Yin + tau L(Yin) with sub_scale = -tau (gamma-1)/rho
 hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind, int stage,
                         const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
-                        const double* coef, hipStream_t st);
+                        const double* coef, hipStream_t st, double sub_scale = 0.0);
 // stages j and j+1 (2 <= j, j+1 < s) in one launch, RKL_MIXED and 3-D grids
 // only; Yj and Yj1 must alias none of Yin, Ym2, Y0
 hipError_t launch_fused2(Variant v, const GridConst& gc, int stage, const double* Yin, const double* Ym2,

@@ -102,6 +102,7 @@ struct StageLaunch {
     double kappa0, kexp, kperp, satq;
     int kmode;
     double fac;
+    double sub_scale;    // kind 3: -tau_sub (gamma-1)/rho
 };
 
 // FIX3: 3-D grid, tile shape fixed at compile time (run_tile's CBX, CBY)
@@ -128,6 +129,8 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
     if (sizeof(R) == 4) tref = st->tref;
     if (a.kind == 0) {
         a.scale = -P.fac;
+    } else if (a.kind == 3) {
+        a.scale = P.sub_scale;
     } else {
         const int s = st->s;
         const double* cf = P.coef + 5 * ((size_t)s * (s + 1) / 2 + P.stage);
@@ -179,7 +182,7 @@ static hipError_t launch_prec(const StageLaunch& P, int nblocks, int bx, int by,
 hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind, int stage,
                         const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
-                        const double* coef, hipStream_t st) {
+                        const double* coef, hipStream_t st, double sub_scale) {
     StageLaunch P;
     TileArgs& a = P.t;
     a.Yin = Yin;
@@ -215,6 +218,7 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
     P.satq = gc.satq;
     P.kmode = gc.kmode;
     P.fac = gc.fac;
+    P.sub_scale = sub_scale;
     const int64_t nb = (int64_t)P.ntx * P.nty * nzc;
     if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
     const bool lim = gc.limiter != 0, sat = gc.saturation != 0;

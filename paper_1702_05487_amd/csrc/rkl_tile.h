@@ -8,6 +8,7 @@
 //   kind 1  MY0 = tau M(Y0),  Y1 = Y0 + mut_1 MY0          (Appendix A, stage 1)
 //   kind 2  Y_j = mu Y_{j-1} + nu Y_{j-2} + (1-mu-nu) Y0 + mut tau M(Y_{j-1})
 //                 + gt MY0                                 (Appendix A, stage j)
+//   kind 3  out = Y + tau (gamma-1)/rho (-div F_c(Y))     (one explicit sub-step)
 // F_c is the face flux of Sec. 2 (Eqs. Fc, Fclass, Fsat plus the
 // perpendicular term) with the transverse gradients of Appendix B.
 //
@@ -449,6 +450,8 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
                 const R m = R(tl);
                 ((R*)a.MY0out)[o] = m;
                 a.Yout[o] = fma(a.mut, (double)m, yq0);
+            } else if (a.kind == 3) {
+                a.Yout[o] = yq0 + tl;
             } else {
                 a.Yout[o] = stage_combine(a.mu, a.nu, a.omn, a.mut, a.gt, yq0, ym2, y0v, tl, (double)my0);
             }

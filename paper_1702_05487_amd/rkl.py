@@ -26,6 +26,7 @@ EXPORTS = [
     "rkl_query", "rkl_variant_count", "rkl_variant_info", "rkl_set_variant", "rkl_last_error",
     "rkl_profile", "rkl_profile_read", "rkl_autotune",
     "rkl_batch_policy_count", "rkl_batch_policy_info", "rkl_set_batch_policy", "rkl_autotune_batched",
+    "rkl_subcycle",
 ]
 
 
@@ -99,6 +100,7 @@ def load(build_if_missing: bool = True):
         "rkl_batch_policy_info": (i32, [i32, P(i32), P(i32)]),
         "rkl_set_batch_policy": (i32, [vp, i32]),
         "rkl_autotune_batched": (i32, [vp, vp, vp, vp, i32, P(i32), P(dbl), vp]),
+        "rkl_subcycle": (i32, [vp, i32, vp, vp, dbl, i64, P(i64), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -144,6 +146,12 @@ def rkl_superstep(plan, grid, T_ptr, b_ptr, dt_hyp, stream):
     s = ctypes.c_int32()
     _check(load().rkl_superstep(plan, grid, T_ptr, b_ptr, float(dt_hyp), ctypes.byref(s), stream))
     return s.value
+
+
+def rkl_subcycle(plan, grid, T_ptr, b_ptr, dt_hyp, max_sub, stream):
+    n = ctypes.c_int64()
+    _check(load().rkl_subcycle(plan, grid, T_ptr, b_ptr, float(dt_hyp), int(max_sub), ctypes.byref(n), stream))
+    return n.value
 
 
 def rkl_superstep_batched(plan, T_ptr, b_ptr, dt_ptr, s_ptr, stream):
@@ -297,6 +305,11 @@ class Plan:
         """Advance T in place by one super-step; returns the stage count."""
         tp, bp = self._tb(grid, T, b)
         return rkl_superstep(self.handle, grid, tp, bp, dt_hyp, _stream())
+
+    def subcycle(self, T, b, dt_hyp, max_sub=1 << 20, grid=0):
+        """Explicit sub-cycling over dt_hyp (T in place); returns the number of sub-steps."""
+        tp, bp = self._tb(grid, T, b)
+        return rkl_subcycle(self.handle, grid, tp, bp, dt_hyp, max_sub, _stream())
 
     def query(self, grid=0):
         return rkl_query(self.handle, grid)
