@@ -5,4 +5,5 @@ CPU-baseline leg may use this package; the product path never does.
 """
 from .oracle import (  # noqa: F401
     Grid, build, load, mc, stages, coeffs, dt_par, flux_div, rkl2_fixed, superstep, subcycle,
+    stages_rkl1, rkl1_fixed, superstep_rkl1,
 )

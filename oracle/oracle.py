@@ -109,6 +109,12 @@ def load():
         lib.orc_rkl2_fixed.restype = None
         lib.orc_superstep.argtypes = [gp, dp, dp, ctypes.c_double, dp]
         lib.orc_subcycle.argtypes = [gp, dp, dp, ctypes.c_double, ctypes.c_long]
+        lib.orc_stages_rkl1.argtypes = [ctypes.c_double]
+        lib.orc_stages_rkl1.restype = ctypes.c_int
+        lib.orc_rkl1_fixed.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double]
+        lib.orc_rkl1_fixed.restype = None
+        lib.orc_superstep_rkl1.argtypes = [gp, dp, dp, ctypes.c_double, dp]
+        lib.orc_superstep_rkl1.restype = ctypes.c_int
         lib.orc_subcycle.restype = ctypes.c_long
         lib.orc_superstep.restype = ctypes.c_int
         _lib = lib
@@ -190,3 +196,27 @@ def subcycle(g: Grid, T, b, dt_hyp: float, max_sub: int = 1 << 20):
     cg = g.c()
     n = load().orc_subcycle(ctypes.byref(cg), _ptr(T), _ptr(b), float(dt_hyp), int(max_sub))
     return T, n
+
+
+def stages_rkl1(r: float) -> int:
+    """RKL1 stage count for dt_hyp/dt_par = r."""
+    return load().orc_stages_rkl1(float(r))
+
+
+def rkl1_fixed(g: Grid, T, b, s: int, tau: float) -> np.ndarray:
+    """s stages of RKL1 over tau; returns Y_s."""
+    T = _field(g, T, "T").copy()
+    b = _bfield(g, b)
+    cg = g.c()
+    load().orc_rkl1_fixed(ctypes.byref(cg), _ptr(T), _ptr(b), int(s), float(tau))
+    return T
+
+
+def superstep_rkl1(g: Grid, T, b, dt_hyp: float):
+    """One RKL1 super-step; returns (T_new, s, dt_par)."""
+    T = _field(g, T, "T").copy()
+    b = _bfield(g, b)
+    cg = g.c()
+    dtp = ctypes.c_double()
+    s = load().orc_superstep_rkl1(ctypes.byref(cg), _ptr(T), _ptr(b), float(dt_hyp), ctypes.byref(dtp))
+    return T, s, dtp.value

@@ -321,3 +321,53 @@ long orc_subcycle(const orc_grid *g, double *T, const double *b, double dt_hyp, 
     free(L);
     return nsub;
 }
+
+/*
+ * RKL1, the first-order Legendre scheme (Sec. 3.3): stability polynomial
+ * R_s(z) = P_s(1 + w1 z) (a_s = 0, b_s = 1 in Eq. stabpara) with
+ * w1 = 2/(s^2+s), and dt_hyp = dt_par (s^2+s)/2 (Eq. RKL-s).  The stages
+ * follow the Legendre recursion (Eq. recLegP) with x = 1 + w1 tau M:
+ *   Y_1 = Y_0 + w1 tau M(Y_0)
+ *   Y_j = (2j-1)/j (Y_{j-1} + w1 tau M(Y_{j-1})) - (j-1)/j Y_{j-2},  j >= 2,
+ * so that Y_s = P_s(1 + w1 tau M) Y_0 for linear M; M is evaluated on each
+ * stage's own temperature.  s = 1 is one forward-Euler step.
+ */
+int orc_stages_rkl1(double r)
+{
+    const double s_real = (-1.0 + sqrt(1.0 + 8.0 * r)) / 2.0;
+    return 1 + (int)floor(s_real);
+}
+
+void orc_rkl1_fixed(const orc_grid *g, double *T, const double *b, int s, double tau)
+{
+    const long N = ncell(g);
+    const double w1 = 2.0 / ((double)s * s + s);
+    double *Yjm2 = malloc(sizeof(double) * N), *Yjm1 = malloc(sizeof(double) * N);
+    double *Yj = malloc(sizeof(double) * N), *L = malloc(sizeof(double) * N);
+
+    memcpy(Yjm2, T, sizeof(double) * N);
+    orc_flux_div(g, Yjm2, b, L);
+    for (long i = 0; i < N; ++i) Yjm1[i] = Yjm2[i] + w1 * tau * L[i];
+
+    for (int j = 2; j <= s; ++j) {
+        orc_flux_div(g, Yjm1, b, L);
+        const double a = (2.0 * j - 1.0) / j, c = (j - 1.0) / j;
+        for (long i = 0; i < N; ++i)
+            Yj[i] = a * (Yjm1[i] + w1 * tau * L[i]) - c * Yjm2[i];
+        double *t = Yjm2; Yjm2 = Yjm1; Yjm1 = Yj; Yj = t;
+    }
+    memcpy(T, Yjm1, sizeof(double) * N);
+    free(Yjm2); free(Yjm1); free(Yj); free(L);
+}
+
+/* One RKL1 super-step of length dt_hyp: dt_par from T, s from the ratio
+ * (rounded up as for RKL2), then the stages.  Returns s. */
+int orc_superstep_rkl1(const orc_grid *g, double *T, const double *b, double dt_hyp, double *dt_par_out)
+{
+    const double dtp = orc_dt_par(g, T);
+    const double r = isinf(dtp) ? 0.0 : dt_hyp / dtp;
+    const int s = orc_stages_rkl1(r);
+    if (dt_par_out) *dt_par_out = dtp;
+    orc_rkl1_fixed(g, T, b, s, dt_hyp);
+    return s;
+}
