@@ -54,6 +54,7 @@ typedef enum {
 } rkl_status;
 
 enum { RKL_FP64 = 0, RKL_MIXED = 1 };   /* flux arithmetic: FP64, or FP32 with FP64 stage recurrence */
+enum { RKL_RKL2 = 0, RKL_RKL1 = 1 };    /* super-step scheme: second- or first-order Legendre (Sec. 3.3) */
 enum { RKL_LIM_NONE = 0, RKL_LIM_MC = 1 };
 
 /* flag bits reported by rkl_query */
@@ -86,7 +87,8 @@ typedef struct {
     int32_t smax;         /* largest stage count accepted (coefficient table size); 0 = 1024
                              for one grid, 64 for several (a batched super-step issues
                              one stage launch per stage up to smax) */
-    int32_t reserved;     /* must be 0 */
+    int32_t scheme;       /* RKL_RKL2 (default) or RKL_RKL1; the batched entry points
+                             implement RKL2 only */
 } rkl_options;
 
 /*
@@ -139,6 +141,11 @@ rkl_status rkl_dt_par(rkl_plan_t plan, int32_t grid, const double *T, double *dt
  * entry point reads it back once (one synchronisation of `stream`) to size
  * the launch sequence, and stores it in *s_out (host pointer, may be NULL).
  * RKL_ESTAGES (T unchanged) if s > smax.  b must not alias T.
+ * With scheme RKL_RKL1 the super-step is the first-order scheme: stability
+ * polynomial P_s(1 + w1 tau lambda), w1 = 2/(s^2+s), stages Y_1 = Y_0 +
+ * w1 tau M(Y_0), Y_j = (2j-1)/j (Y_{j-1} + w1 tau M(Y_{j-1})) - (j-1)/j Y_{j-2},
+ * and s from dt_hyp = dt_par (s^2+s)/2 rounded as for RKL2 (s >= 1; s = 1 is
+ * one forward-Euler step).
  */
 rkl_status rkl_superstep(rkl_plan_t plan, int32_t grid, double *T, const void *b,
                          double dt_hyp, int32_t *s_out, void *stream);

@@ -34,6 +34,7 @@ struct rkl_plan_s {
     int precision = RKL_FP64;
     int variant = 0;
     int smax = 1024;
+    int scheme = RKL_RKL2;
     std::vector<rkl_grid_desc> desc;
     std::vector<GridConst> gc;
     std::vector<int64_t> off;   // packed cell offsets, ngrids + 1 entries
@@ -77,9 +78,28 @@ static void prof_clear(rkl_plan_s* p) {
 // mut_1 = b_1 w1, mu_j = (2j-1)/j b_j/b_{j-1}, nu_j = -(j-1)/j b_j/b_{j-2},
 // mut_j = mu_j w1, gt_j = -a_{j-1} mut_j.  Row j of s holds
 // {mu_j, nu_j, 1 - mu_j - nu_j, mut_j, gt_j} at 5 (s(s+1)/2 + j).
-static std::vector<double> coefficient_table(int smax) {
+// RKL1 (Sec. 3.3: P_s(1 + w1 z), w1 = 2/(s^2+s), Legendre recursion): mut_1 =
+// w1; mu_j = (2j-1)/j, nu_j = -(j-1)/j, mut_j = mu_j w1, and no Y0 or tau
+// M(Y0) term (1 - mu_j - nu_j = 0, gt_j = 0).
+static std::vector<double> coefficient_table(int smax, int scheme) {
     const size_t rows = (size_t)(smax + 1) * (smax + 2) / 2;
     std::vector<double> t(rows * 5, 0.0);
+    if (scheme == RKL_RKL1) {
+        for (int s = 1; s <= smax; ++s) {
+            const double w1 = 2.0 / ((double)s * s + s);
+            double* row = &t[5 * ((size_t)s * (s + 1) / 2)];
+            row[5 * 1 + 3] = w1;
+            for (int j = 2; j <= s; ++j) {
+                double* r = row + 5 * j;
+                r[0] = (2.0 * j - 1.0) / j;
+                r[1] = -(j - 1.0) / j;
+                r[2] = 0.0;
+                r[3] = r[0] * w1;
+                r[4] = 0.0;
+            }
+        }
+        return t;
+    }
     std::vector<double> bj(smax + 1);
     for (int j = 0; j <= smax; ++j)
         bj[j] = j <= 2 ? 1.0 / 3.0 : ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
@@ -124,7 +144,7 @@ static bool validate(const rkl_grid_desc& g, std::string& why) {
     return true;
 }
 
-static GridConst make_const(const rkl_grid_desc& g) {
+static GridConst make_const(const rkl_grid_desc& g, int scheme) {
     GridConst c;
     c.n0 = g.n[0];
     c.n1 = g.n[1];
@@ -140,6 +160,7 @@ static GridConst make_const(const rkl_grid_desc& g) {
     c.kmode = g.kappa_exp == 0.0 ? 0 : (g.kappa_exp == 2.5 ? 1 : 2);
     c.limiter = g.limiter;
     c.saturation = g.saturation;
+    c.scheme = scheme;
     c.fac = (g.gamma - 1.0) / g.rho;
     c.cp = g.cp;
     double s = 0.0;
@@ -169,6 +190,8 @@ static void free_plan(rkl_plan_s* p) {
 
 static rkl_status ensure_batch(rkl_plan_s* p) {
     if (p->batch) return RKL_OK;
+    // the batched stage routing writes stage j = s into T, which needs s >= 2
+    if (p->scheme != RKL_RKL2) return fail(RKL_EINVAL, "the batched super-step implements RKL2 only");
     std::string why;
     rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, p->batch_policy, &p->batch, why);
     return st == RKL_OK ? RKL_OK : fail(st, why);
@@ -308,13 +331,14 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
     if (o.smax == 0) o.smax = ngrids > 1 ? 64 : 1024;
     if (o.smax < 2 || o.smax > 4096) return fail(RKL_EINVAL, "smax must be in [2, 4096]");
     if (o.variant < -1 || o.variant >= variant_count()) return fail(RKL_EINVAL, "variant out of range");
-    if (o.reserved != 0) return fail(RKL_EINVAL, "rkl_options.reserved must be 0");
+    if (o.scheme != RKL_RKL2 && o.scheme != RKL_RKL1) return fail(RKL_EINVAL, "scheme must be RKL_RKL2 or RKL_RKL1");
 
     rkl_plan_s* p = new rkl_plan_s();
     p->ngrids = ngrids;
     p->precision = o.precision;
     p->variant = 0;
     p->smax = o.smax;
+    p->scheme = o.scheme;
     p->off.push_back(0);
     for (int g = 0; g < ngrids; ++g) {
         std::string why;
@@ -323,7 +347,7 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
             return fail(RKL_EINVAL, "grid " + std::to_string(g) + ": " + why);
         }
         p->desc.push_back(grids[g]);
-        p->gc.push_back(make_const(grids[g]));
+        p->gc.push_back(make_const(grids[g], o.scheme));
         const int64_t n = (int64_t)grids[g].n[0] * grids[g].n[1] * grids[g].n[2];
         p->off.push_back(p->off.back() + n);
     }
@@ -332,7 +356,7 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
     if (e != hipSuccess) { free_plan(p); return hipfail(e, "hipGetDevice"); }
 
     const size_t rs = o.precision == RKL_MIXED ? sizeof(float) : sizeof(double);
-    const std::vector<double> tab = coefficient_table(o.smax);
+    const std::vector<double> tab = coefficient_table(o.smax, o.scheme);
     bool ok = hipMalloc(&p->Ya, sizeof(double) * p->total) == hipSuccess &&
               hipMalloc(&p->Yb, sizeof(double) * p->total) == hipSuccess &&
               hipMalloc(&p->MY0, rs * p->total) == hipSuccess &&
@@ -349,7 +373,7 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
     e = hipMemcpy(p->coef, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->state, 0, sizeof(GridState) * ngrids);
     if (e != hipSuccess) { free_plan(p); return hipfail(e, "plan upload"); }
-    if (ngrids > 1) {
+    if (ngrids > 1 && o.scheme == RKL_RKL2) {
         std::string why;
         rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, 0, &p->batch, why);
         if (st != RKL_OK) { free_plan(p); return fail(st, why); }
@@ -442,8 +466,10 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
     HIPCHECK(hipStreamSynchronize(s), "s sync");
     const int S = *p->s_host;
     if (s_out) *s_out = S;
-    if (S < 2 || S > p->smax)
-        return fail(RKL_ESTAGES, "stage count " + std::to_string(S) + " outside [2, smax=" + std::to_string(p->smax) + "]");
+    const int smin = p->scheme == RKL_RKL1 ? 1 : 2;
+    if (S < smin || S > p->smax)
+        return fail(RKL_ESTAGES, "stage count " + std::to_string(S) + " outside [" + std::to_string(smin) +
+                                     ", smax=" + std::to_string(p->smax) + "]");
 
     const GridConst& gc = p->gc[g];
     const Variant v = variant_get(p->variant);
@@ -505,6 +531,8 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
         }
         j += done;
     }
+    if (S == 1)   // RKL1 with one stage: Y1 was written next to T (stage 1 reads T around each cell)
+        HIPCHECK(hipMemcpyAsync(T, bufs[0], sizeof(double) * n, hipMemcpyDeviceToDevice, s), "result copy");
     return RKL_OK;
 }
 

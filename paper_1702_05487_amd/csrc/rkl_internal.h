@@ -24,6 +24,7 @@ struct GridConst {
     double kappa0, kexp, kperp, satq;  // satq = 5 phi rho
     int kmode;              // 0: kappa0, 1: kappa0 T^2.5, 2: kappa0 T^kexp
     int limiter, saturation;
+    int scheme;             // 0 RKL2, 1 RKL1
     double fac;             // (gamma-1)/rho
     double cp, ihsum;       // Courant number, sum_d 1/h_d^2 over active axes
 };
@@ -40,8 +41,9 @@ __device__ inline double kappa_at(const GridConst& g, double T) {
 // Turn the temperature maximum/minimum of a grid into its state: dt_par of
 // Eq. dt_exp with chi = kappa_par (gamma-1)/rho (kappa_par is non-decreasing
 // in T, so its maximum over cells is kappa_par(max T)) and, for a super-step
-// (mode 0), the stage count of Eq. RKL-s, dt_hyp = dt_par (s^2+s-2)/4, with
-// its root rounded up as 1 + floor(s).  flag bits as in rkl.h.
+// (mode 0), the stage count of Eq. RKL-s -- dt_hyp = dt_par (s^2+s-2)/4 for
+// RKL2, dt_par (s^2+s)/2 for RKL1 -- with its root rounded up as
+// 1 + floor(s).  flag bits as in rkl.h.
 __device__ inline GridState finalize_state(const GridConst& g, double mx, double mn, bool bad,
                                            double dt_hyp, int mode, int smax) {
 #pragma clang fp contract(off)
@@ -53,7 +55,8 @@ __device__ inline GridState finalize_state(const GridConst& g, double mx, double
     int32_t s = 0;
     if (mode == 0) {
         const double r = isinf(dtp) ? 0.0 : dt_hyp / dtp;
-        const double sr = (-1.0 + sqrt(9.0 + 16.0 * r)) / 2.0;
+        const double sr = g.scheme == 1 ? (-1.0 + sqrt(1.0 + 8.0 * r)) / 2.0
+                                        : (-1.0 + sqrt(9.0 + 16.0 * r)) / 2.0;
         const double sf = floor(sr);
         s = (sf >= 0.0 && sf < 1e9) ? 1 + (int32_t)sf : 0x7fffffff;
         if (s > smax) flags |= 4u; // RKL_FLAG_STAGES

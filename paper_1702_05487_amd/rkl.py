@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "librkl.so")
 RKL_OK, RKL_EINVAL, RKL_ENOMEM, RKL_EDEVICE, RKL_ESTAGES, RKL_ESTATE = range(6)
 RKL_FP64, RKL_MIXED = 0, 1
 RKL_LIM_NONE, RKL_LIM_MC = 0, 1
+RKL_RKL2, RKL_RKL1 = 0, 1
 RKL_FLAG_NONPOS, RKL_FLAG_NONFINITE, RKL_FLAG_STAGES = 1, 2, 4
 
 EXPORTS = [
@@ -52,7 +53,7 @@ class rkl_options(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("variant", ctypes.c_int32),
         ("smax", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
     ]
 
 
@@ -116,9 +117,9 @@ def _check(status):
 
 
 # -------------------------------------------------- raw C entry points ----
-def rkl_plan(descs, precision=RKL_FP64, variant=-1, smax=0):
+def rkl_plan(descs, precision=RKL_FP64, variant=-1, smax=0, scheme=RKL_RKL2):
     arr = (rkl_grid_desc * len(descs))(*descs)
-    opt = rkl_options(precision, variant, smax, 0)
+    opt = rkl_options(precision, variant, smax, scheme)
     h = ctypes.c_void_p()
     _check(load().rkl_plan(arr, len(descs), ctypes.byref(opt), ctypes.byref(h)))
     return h
@@ -265,12 +266,13 @@ def _dev_ptr(t, dtype, numel, name):
 class Plan:
     """A librkl plan over one grid or a batch of grids (descs: rkl_grid_desc list)."""
 
-    def __init__(self, descs, precision="fp64", variant=-1, smax=0):
+    def __init__(self, descs, precision="fp64", variant=-1, smax=0, scheme="rkl2"):
         import torch
         self.descs = list(descs)
         self.precision = RKL_MIXED if precision in ("mixed", RKL_MIXED) else RKL_FP64
+        self.scheme = RKL_RKL1 if scheme in ("rkl1", RKL_RKL1) else RKL_RKL2
         self.bdtype = torch.float32 if self.precision == RKL_MIXED else torch.float64
-        self.handle = rkl_plan(self.descs, self.precision, variant, smax)
+        self.handle = rkl_plan(self.descs, self.precision, variant, smax, self.scheme)
         self.cells = [d.n[0] * d.n[1] * d.n[2] for d in self.descs]
 
     def close(self):

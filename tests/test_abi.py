@@ -62,7 +62,7 @@ def test_invalid_descriptors_are_rejected(bad):
 
 def test_invalid_options_are_rejected():
     d = rkl.grid_desc((8, 8, 8), (0.1,) * 3)
-    for kw in (dict(precision=7), dict(smax=1), dict(smax=5000), dict(variant=999)):
+    for kw in (dict(precision=7), dict(smax=1), dict(smax=5000), dict(variant=999), dict(scheme=2)):
         with pytest.raises(rkl.RklError) as e:
             rkl.rkl_plan([d], **kw)
         assert e.value.status == rkl.RKL_EINVAL
