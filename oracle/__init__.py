@@ -5,5 +5,5 @@ CPU-baseline leg may use this package; the product path never does.
 """
 from .oracle import (  # noqa: F401
     Grid, build, load, mc, stages, coeffs, dt_par, flux_div, rkl2_fixed, superstep, subcycle,
-    stages_rkl1, rkl1_fixed, superstep_rkl1,
+    stages_rkl1, rkl1_fixed, superstep_rkl1, aag_gain, aag_stages, aag_taus, aag_fixed, aag_superstep,
 )

@@ -109,6 +109,16 @@ def load():
         lib.orc_rkl2_fixed.restype = None
         lib.orc_superstep.argtypes = [gp, dp, dp, ctypes.c_double, dp]
         lib.orc_subcycle.argtypes = [gp, dp, dp, ctypes.c_double, ctypes.c_long]
+        lib.orc_aag_gain.argtypes = [ctypes.c_int, ctypes.c_double]
+        lib.orc_aag_gain.restype = ctypes.c_double
+        lib.orc_aag_stages.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        lib.orc_aag_stages.restype = ctypes.c_int
+        lib.orc_aag_taus.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
+        lib.orc_aag_taus.restype = None
+        lib.orc_aag_fixed.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        lib.orc_aag_fixed.restype = None
+        lib.orc_aag_superstep.argtypes = [gp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        lib.orc_aag_superstep.restype = ctypes.c_int
         lib.orc_stages_rkl1.argtypes = [ctypes.c_double]
         lib.orc_stages_rkl1.restype = ctypes.c_int
         lib.orc_rkl1_fixed.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double]
@@ -220,3 +230,36 @@ def superstep_rkl1(g: Grid, T, b, dt_hyp: float):
     dtp = ctypes.c_double()
     s = load().orc_superstep_rkl1(ctypes.byref(cg), _ptr(T), _ptr(b), float(dt_hyp), ctypes.byref(dtp))
     return T, s, dtp.value
+
+
+def aag_gain(s: int, nu: float) -> float:
+    """AAG-STS gain (sum of the sub-steps over dt_par), Eq. AAG-STS."""
+    return load().orc_aag_gain(int(s), float(nu))
+
+
+def aag_stages(r: float, nu: float, smax: int = 4096) -> int:
+    return load().orc_aag_stages(float(r), float(nu), int(smax))
+
+
+def aag_taus(s: int, nu: float, dt_p: float) -> np.ndarray:
+    out = np.empty(s)
+    load().orc_aag_taus(int(s), float(nu), float(dt_p), _ptr(out))
+    return out
+
+
+def aag_superstep(g: Grid, T, b, dt_hyp: float, nu: float, smax: int = 4096):
+    """One AAG super-step; returns (T_new, s)."""
+    T = _field(g, T, "T").copy()
+    b = _bfield(g, b)
+    cg = g.c()
+    s = load().orc_aag_superstep(ctypes.byref(cg), _ptr(T), _ptr(b), float(dt_hyp), float(nu), int(smax))
+    return T, s
+
+
+def aag_fixed(g: Grid, T, b, s: int, nu: float, dt_hyp: float) -> np.ndarray:
+    """s AAG sub-steps scaled to sum to dt_hyp; returns the result."""
+    T = _field(g, T, "T").copy()
+    b = _bfield(g, b)
+    cg = g.c()
+    load().orc_aag_fixed(ctypes.byref(cg), _ptr(T), _ptr(b), int(s), float(nu), float(dt_hyp))
+    return T

@@ -371,3 +371,64 @@ int orc_superstep_rkl1(const orc_grid *g, double *T, const double *b, double dt_
     orc_rkl1_fixed(g, T, b, s, dt_hyp);
     return s;
 }
+
+/*
+ * AAG super-time-stepping (Alexiades, Amiez & Gremaud 1996; Sec. 3.3): s
+ * forward-Euler sub-steps with the damped Chebyshev sequence
+ *   tau_j = dt_p / ((nu - 1) cos(pi (2j - 1) / (2s)) + 1 + nu),  j = 1..s,
+ * whose sum is the gain of Eq. AAG-STS,
+ *   dt_p s / (2 sqrt(nu)) [(1+sqrt(nu))^{2s} - (1-sqrt(nu))^{2s}]
+ *                         / [(1+sqrt(nu))^{2s} + (1-sqrt(nu))^{2s}].
+ * orc_aag_gain returns that bracket times s/(2 sqrt(nu)) (the sum over dt_p);
+ * orc_aag_stages the smallest s whose gain reaches r = dt_hyp/dt_par;
+ * orc_aag_superstep scales the sequence of that s to sum to dt_hyp (each
+ * sub-step then stays within the sequence built on dt_par) and applies it.
+ */
+double orc_aag_gain(int s, double nu)
+{
+    const double q = sqrt(nu);
+    const double a = pow(1.0 + q, 2.0 * s), c = pow(1.0 - q, 2.0 * s);
+    return s / (2.0 * q) * (a - c) / (a + c);
+}
+
+int orc_aag_stages(double r, double nu, int smax)
+{
+    for (int s = 1; s <= smax; ++s)
+        if (orc_aag_gain(s, nu) >= r) return s;
+    return -1;
+}
+
+void orc_aag_taus(int s, double nu, double dt_p, double *tau)
+{
+    const double pi = 3.14159265358979323846;
+    for (int j = 1; j <= s; ++j)
+        tau[j - 1] = dt_p / ((nu - 1.0) * cos(pi * (2.0 * j - 1.0) / (2.0 * s)) + 1.0 + nu);
+}
+
+/* s AAG sub-steps whose sequence is scaled to sum to dt_hyp */
+void orc_aag_fixed(const orc_grid *g, double *T, const double *b, int s, double nu, double dt_hyp)
+{
+    double *tau = malloc(sizeof(double) * s);
+    orc_aag_taus(s, nu, 1.0, tau);
+    double sum = 0.0;
+    for (int j = 0; j < s; ++j) sum += tau[j];
+    const long N = ncell(g);
+    double *L = malloc(sizeof(double) * N);
+    for (int j = 0; j < s; ++j) {
+        const double t = tau[j] * (dt_hyp / sum);
+        orc_flux_div(g, T, b, L);
+        for (long i = 0; i < N; ++i) T[i] = T[i] + t * L[i];
+    }
+    free(L);
+    free(tau);
+}
+
+int orc_aag_superstep(const orc_grid *g, double *T, const double *b, double dt_hyp, double nu, int smax)
+{
+    const double dtp = orc_dt_par(g, T);
+    if (!(dt_hyp > 0.0) || isinf(dtp)) return 0;
+    const int s = orc_aag_stages(dt_hyp / dtp, nu, smax);
+    if (s < 0) return -1;
+    orc_aag_fixed(g, T, b, s, nu, dt_hyp);
+    return s;
+}
