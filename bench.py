@@ -229,9 +229,9 @@ def bench_batched(args, torch, inputs, rkl):
 def bench_subcycle(args, torch, inputs, rkl):
     """Explicit sub-cycling (N_sub = ceil(dt_hyp/dt_par) forward-Euler
     sub-steps) of the 256^3 FP64 workload over the dt_hyp that gives its
-    RKL2 super-step s = 16, against that super-step (and the RKL1 one) on
-    the same fields: the measured speed-up of super-time-stepping over
-    sub-cycling on this GPU.  One step = one dt_hyp interval; value =
+    RKL2 super-step s = 16, against that super-step (and the RKL1 and AAG
+    ones) on the same fields: the measured speed-up of super-time-stepping
+    over sub-cycling on this GPU.  One step = one dt_hyp interval; value =
     cell-sub-steps per second."""
     dev = torch.device("cuda:0")
     w = inputs.spitzer_256(device=dev)
@@ -264,6 +264,7 @@ def bench_subcycle(args, torch, inputs, rkl):
     plan1 = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision="fp64", scheme="rkl1")
     sec_rkl1, stages1 = timed(lambda: plan1.superstep(T, b, dt))
     plan1.close()
+    sec_aag, stages_aag = timed(lambda: plan.aag(T, b, dt, 0.01))
     rkl.rkl_profile(plan.handle, 1)
     sec_sub, nsub = timed(lambda: plan.subcycle(T, b, dt))
     ms, launches, _ = rkl.rkl_profile_read(plan.handle, 3)
@@ -297,6 +298,8 @@ def bench_subcycle(args, torch, inputs, rkl):
             "sts_speedup": sec_sub / sec_sts,
             "rkl1_stages_same_dt": stages1 // args.steps,
             "rkl1_ms_per_step": sec_rkl1 * 1e3 / args.steps,
+            "aag_nu": 0.01, "aag_stages_same_dt": stages_aag // args.steps,
+            "aag_ms_per_step": sec_aag * 1e3 / args.steps,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",

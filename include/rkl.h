@@ -166,6 +166,20 @@ rkl_status rkl_subcycle(rkl_plan_t plan, int32_t grid, double *T, const void *b,
                         int64_t max_sub, int64_t *nsub_out, void *stream);
 
 /*
+ * rkl_aag: one AAG super-time-step (Alexiades, Amiez & Gremaud 1996; the
+ * first-order scheme the paper compares RKL with, Sec. 3.3) of length
+ * dt_hyp on one grid, T updated in place: S forward-Euler sub-steps with the
+ * damped Chebyshev sequence tau_j = dt_par / ((nu-1) cos(pi (2j-1)/(2S)) +
+ * 1 + nu), j = 1..S, scaled to sum to dt_hyp, where S is the smallest count
+ * whose gain (Eq. AAG-STS) reaches dt_hyp/dt_par.  nu in (0, 1) is the
+ * damping.  Reads dt_par back once (one synchronisation); *s_out (host, may
+ * be NULL) receives S (0: nothing to do).  RKL_ESTAGES (T unchanged) if S
+ * would exceed max_s.  Same kernels and ping-pong as rkl_subcycle.
+ */
+rkl_status rkl_aag(rkl_plan_t plan, int32_t grid, double *T, const void *b, double dt_hyp, double nu,
+                   int32_t max_s, int32_t *s_out, void *stream);
+
+/*
  * rkl_superstep_batched: one super-step of every grid of the plan at once
  * with no host synchronisation -- safe to capture in a HIP graph: one
  * reduce launch (dt_par and s per grid on the device), then one launch per
@@ -220,9 +234,10 @@ rkl_status rkl_set_variant(rkl_plan_t plan, int32_t variant);
  * a pair of HIP events on the caller's stream around each stencil launch of
  * stages j >= 2 of every following rkl_superstep and (eager, not captured)
  * rkl_superstep_batched (the dominant kernels) and around each sub-step
- * launch of rkl_subcycle; rkl_profile(plan, 0) stops and discards.
+ * launch of rkl_subcycle and rkl_aag; rkl_profile(plan, 0) stops and
+ * discards.
  * rkl_profile_read synchronises and returns, over the launches of one kind
- * -- `fuse` 1: one-stage, 2: two-stage, 3: sub-cycling -- the summed
+ * -- `fuse` 1: one-stage, 2: two-stage, 3: forward-Euler sub-steps -- the summed
  * duration in ms, the number of launches and of cell updates (batched
  * launches count 0: their work follows from the device-side stage counts).
  */

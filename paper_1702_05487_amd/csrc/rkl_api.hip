@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -536,33 +537,16 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
     return RKL_OK;
 }
 
-rkl_status rkl_subcycle(rkl_plan_t p, int32_t g, double* T, const void* b, double dt_hyp, int64_t max_sub,
-                        int64_t* nsub_out, void* stream) {
-    rkl_status st = check_grid(p, g);
-    if (st != RKL_OK) return st;
-    if (nsub_out) *nsub_out = 0;
-    if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
-    if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
-    if (max_sub < 1) return fail(RKL_EINVAL, "max_sub must be >= 1");
-    hipStream_t s = (hipStream_t)stream;
-    st = reduce_and_finalize(p, g, T, 0.0, 1, nullptr, s);
-    if (st != RKL_OK) return st;
-    double dtp = 0.0;
-    HIPCHECK(hipMemcpyAsync(&dtp, &p->state[g].dt_par, sizeof(double), hipMemcpyDeviceToHost, s), "dt_par copy");
-    HIPCHECK(hipStreamSynchronize(s), "dt_par sync");
-    if (dt_hyp == 0.0 || std::isinf(dtp)) return RKL_OK;   // nothing to do
-    // N_sub = ceil(dt_hyp / dt_par) forward-Euler sub-steps of dt_hyp / N_sub
-    const double q = std::ceil(dt_hyp / dtp);
-    if (!(q <= (double)max_sub))
-        return fail(RKL_ESTAGES, "sub-step count above max_sub (T unchanged)");
-    const int64_t nsub = (int64_t)q;
-    const double sub_scale = -(dt_hyp / (double)nsub) * p->gc[g].fac;
+// Forward-Euler sub-steps T <- T + tau_k (gamma-1)/rho (-div F_c(T)), one
+// launch each (stage kernel kind 3), ping-ponging between T and the plan's
+// first stage buffer; an odd count ends with one copy into T.
+static rkl_status euler_substeps(rkl_plan_t p, int32_t g, double* T, const void* b, int64_t count,
+                                 const std::function<double(int64_t)>& tau, hipStream_t s) {
     const GridConst& gc = p->gc[g];
     const Variant v = variant_get(p->variant);
     const int64_t n = p->off[g + 1] - p->off[g];
     double* A = p->Ya + p->off[g];
-    for (int64_t k = 0; k < nsub; ++k) {
-        // T -> A -> T -> ...; an odd count leaves the result in A
+    for (int64_t k = 0; k < count; ++k) {
         const double* in = (k % 2 == 0) ? T : A;
         double* out = (k % 2 == 0) ? A : T;
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -578,7 +562,7 @@ rkl_status rkl_subcycle(rkl_plan_t p, int32_t g, double* T, const void* b, doubl
             HIPCHECK(hipEventRecord(e0, s), "event record");
         }
         HIPCHECK(launch_stage(p->precision, v, gc, 3, 0, in, nullptr, nullptr, nullptr, nullptr, out, b,
-                              p->state + g, p->coef, s, sub_scale),
+                              p->state + g, p->coef, s, -tau(k) * gc.fac),
                  "sub-step launch");
         if (p->prof) {
             HIPCHECK(hipEventRecord(e1, s), "event record");
@@ -586,9 +570,82 @@ rkl_status rkl_subcycle(rkl_plan_t p, int32_t g, double* T, const void* b, doubl
             p->prof_recs[rec].cells = n;
         }
     }
-    if (nsub % 2 == 1)
+    if (count % 2 == 1)
         HIPCHECK(hipMemcpyAsync(T, A, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "result copy");
+    return RKL_OK;
+}
+
+// dt_par of grid g from T (reduction + one read-back)
+static rkl_status read_dt_par(rkl_plan_t p, int32_t g, const double* T, double* dtp, hipStream_t s) {
+    rkl_status st = reduce_and_finalize(p, g, T, 0.0, 1, nullptr, s);
+    if (st != RKL_OK) return st;
+    HIPCHECK(hipMemcpyAsync(dtp, &p->state[g].dt_par, sizeof(double), hipMemcpyDeviceToHost, s), "dt_par copy");
+    HIPCHECK(hipStreamSynchronize(s), "dt_par sync");
+    return RKL_OK;
+}
+
+rkl_status rkl_subcycle(rkl_plan_t p, int32_t g, double* T, const void* b, double dt_hyp, int64_t max_sub,
+                        int64_t* nsub_out, void* stream) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    if (nsub_out) *nsub_out = 0;
+    if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
+    if (max_sub < 1) return fail(RKL_EINVAL, "max_sub must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    double dtp = 0.0;
+    st = read_dt_par(p, g, T, &dtp, s);
+    if (st != RKL_OK) return st;
+    if (dt_hyp == 0.0 || std::isinf(dtp)) return RKL_OK;   // nothing to do
+    // N_sub = ceil(dt_hyp / dt_par) forward-Euler sub-steps of dt_hyp / N_sub
+    const double q = std::ceil(dt_hyp / dtp);
+    if (!(q <= (double)max_sub))
+        return fail(RKL_ESTAGES, "sub-step count above max_sub (T unchanged)");
+    const int64_t nsub = (int64_t)q;
+    const double tau = dt_hyp / (double)nsub;
+    st = euler_substeps(p, g, T, b, nsub, [tau](int64_t) { return tau; }, s);
+    if (st != RKL_OK) return st;
     if (nsub_out) *nsub_out = nsub;
+    return RKL_OK;
+}
+
+// AAG gain (the sum of the sub-steps over dt_par) of s stages, Eq. AAG-STS
+static double aag_gain(int s, double nu) {
+    const double q = std::sqrt(nu);
+    const double a = std::pow(1.0 + q, 2.0 * s), c = std::pow(1.0 - q, 2.0 * s);
+    return s / (2.0 * q) * ((a - c) / (a + c));
+}
+
+rkl_status rkl_aag(rkl_plan_t p, int32_t g, double* T, const void* b, double dt_hyp, double nu, int32_t max_s,
+                   int32_t* s_out, void* stream) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    if (s_out) *s_out = 0;
+    if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
+    if (!(nu > 0.0 && nu < 1.0)) return fail(RKL_EINVAL, "nu must be in (0, 1)");
+    if (max_s < 1) return fail(RKL_EINVAL, "max_s must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    double dtp = 0.0;
+    st = read_dt_par(p, g, T, &dtp, s);
+    if (st != RKL_OK) return st;
+    if (dt_hyp == 0.0 || std::isinf(dtp)) return RKL_OK;
+    const double r = dt_hyp / dtp;
+    int S = -1;
+    for (int k = 1; k <= max_s; ++k)
+        if (aag_gain(k, nu) >= r) { S = k; break; }
+    if (S < 0) return fail(RKL_ESTAGES, "AAG stage count above max_s (T unchanged)");
+    // tau_j = dt_p / ((nu-1) cos(pi (2j-1)/(2S)) + 1 + nu), scaled to sum to dt_hyp
+    std::vector<double> taus(S);
+    double sum = 0.0;
+    for (int j = 1; j <= S; ++j) {
+        taus[j - 1] = 1.0 / ((nu - 1.0) * std::cos(M_PI * (2.0 * j - 1.0) / (2.0 * S)) + 1.0 + nu);
+        sum += taus[j - 1];
+    }
+    for (double& t : taus) t *= dt_hyp / sum;
+    st = euler_substeps(p, g, T, b, S, [&taus](int64_t k) { return taus[k]; }, s);
+    if (st != RKL_OK) return st;
+    if (s_out) *s_out = S;
     return RKL_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "rkl_query", "rkl_variant_count", "rkl_variant_info", "rkl_set_variant", "rkl_last_error",
     "rkl_profile", "rkl_profile_read", "rkl_autotune",
     "rkl_batch_policy_count", "rkl_batch_policy_info", "rkl_set_batch_policy", "rkl_autotune_batched",
-    "rkl_subcycle",
+    "rkl_subcycle", "rkl_aag",
 ]
 
 
@@ -102,6 +102,7 @@ def load(build_if_missing: bool = True):
         "rkl_set_batch_policy": (i32, [vp, i32]),
         "rkl_autotune_batched": (i32, [vp, vp, vp, vp, i32, P(i32), P(dbl), vp]),
         "rkl_subcycle": (i32, [vp, i32, vp, vp, dbl, i64, P(i64), vp]),
+        "rkl_aag": (i32, [vp, i32, vp, vp, dbl, dbl, i32, P(i32), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -152,6 +153,12 @@ def rkl_superstep(plan, grid, T_ptr, b_ptr, dt_hyp, stream):
 def rkl_subcycle(plan, grid, T_ptr, b_ptr, dt_hyp, max_sub, stream):
     n = ctypes.c_int64()
     _check(load().rkl_subcycle(plan, grid, T_ptr, b_ptr, float(dt_hyp), int(max_sub), ctypes.byref(n), stream))
+    return n.value
+
+
+def rkl_aag(plan, grid, T_ptr, b_ptr, dt_hyp, nu, max_s, stream):
+    n = ctypes.c_int32()
+    _check(load().rkl_aag(plan, grid, T_ptr, b_ptr, float(dt_hyp), float(nu), int(max_s), ctypes.byref(n), stream))
     return n.value
 
 
@@ -312,6 +319,11 @@ class Plan:
         """Explicit sub-cycling over dt_hyp (T in place); returns the number of sub-steps."""
         tp, bp = self._tb(grid, T, b)
         return rkl_subcycle(self.handle, grid, tp, bp, dt_hyp, max_sub, _stream())
+
+    def aag(self, T, b, dt_hyp, nu, max_s=4096, grid=0):
+        """One AAG super-time-step with damping nu (T in place); returns the stage count."""
+        tp, bp = self._tb(grid, T, b)
+        return rkl_aag(self.handle, grid, tp, bp, dt_hyp, nu, max_s, _stream())
 
     def query(self, grid=0):
         return rkl_query(self.handle, grid)
