@@ -11,9 +11,10 @@
 // are dispatched largest grid first so that the small tiles fill the tail of
 // each launch.
 //
-// Tile shapes are chosen per grid so that a patch narrower than 64 cells is
-// covered by full-width rows (no ragged x tiles); every tile runs the same
-// run_tile code as the single-grid kernels.
+// Tile shapes are chosen per grid by a tile policy (z-chunk length; full- or
+// half-width rows, so that a patch narrower than 64 cells has no ragged x
+// tiles); every tile runs the same run_tile code as the single-grid kernels,
+// so the policy never changes the result.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -159,9 +160,6 @@ __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int
     batch_tile<R, LIM, SAT, KM>(P, it.x, stage, it.y, st, L);
 }
 
-// tile shape for one grid: full-width rows when the grid is at most 64 cells
-// wide, as many rows as fit 256 threads (at most 64), the whole z extent up
-// to 32 planes per tile
 // Tile policies of the batched launch: z-chunk length and row width.  Rows
 // are the grid's full width (up to 64 cells), or half of it for grids wider
 // than 32 cells (twice the tiles, shorter halo rows); by fills the 256
