@@ -237,3 +237,43 @@ def patch_set(npatch: int = 2000, seed: int = 7, fields: bool = True,
             ps.b.append(tangled_b(n, 1000 + 2 * p, kmax=kmax, box=box, device=device))
             ps.T.append(noisy_temperature(n, 1001 + 2 * p, kmax=kmax, device=device))
     return ps
+
+
+# --------------------------------------------------------------------------
+# The paper's validation problems (Sec. 4.1.2 and 4.1.3).  Both are periodic;
+# only the initial fields and parameters are made here.
+# --------------------------------------------------------------------------
+
+RING_PARAMS = dict(BASE)              # kappa_par = 1, kappa_perp = 0, no saturation
+
+
+def ring(N: int):
+    """Ring diffusion (Sec. 4.1.3): [-1, 1]^2 with N x N cells, circular field
+    lines b = (y, -x)/r, T = 12 inside the arc 11pi/12 <= theta <= 13pi/12,
+    0.5 <= r <= 0.7, else 10.  Returns (T (1, N, N), b (3, 1, N, N), h)."""
+    h = 2.0 / N
+    x = -1.0 + (np.arange(N) + 0.5) * h
+    X, Y = np.meshgrid(x, x)
+    r = np.hypot(X, Y)
+    th = np.mod(np.arctan2(Y, X), 2.0 * np.pi)
+    arc = (th >= 11.0 * np.pi / 12.0) & (th <= 13.0 * np.pi / 12.0) & (r >= 0.5) & (r <= 0.7)
+    T = np.where(arc, 12.0, 10.0)
+    b = np.zeros((3, 1, N, N))
+    b[0, 0] = Y / r
+    b[1, 0] = -X / r
+    return T[None], b, h
+
+
+SAWTOOTH_PARAMS = dict(BASE, kappa0=40.0, saturation=1, phi=0.3)
+
+
+def sawtooth(N: int = 400, L: float = 20.0):
+    """Saw-tooth profile (Sec. 4.1.2): x in [-L/2, L/2) with N cells,
+    T = 10 + 20 (x/10 - floor(x/10 + 1/2)) (period 10, range [0, 20)), field
+    along x.  Returns (T (1, 1, N), b (3, 1, 1, N), h)."""
+    h = L / N
+    x = -L / 2.0 + (np.arange(N) + 0.5) * h
+    T = 10.0 + 20.0 * (x / 10.0 - np.floor(x / 10.0 + 0.5))
+    b = np.zeros((3, 1, 1, N))
+    b[0] = 1.0
+    return T[None, None], b, h
