@@ -31,8 +31,11 @@
  *   normalised sum of the two cell unit vectors (zero when that sum is
  *   shorter than 1e-12); the limited transverse gradient at a face is
  *   MC(MC(a1,a2), MC(a3,a4)) over the one-sided differences of the two cells,
- *   the unlimited one is their mean; the saturated flux is central, with the
- *   full face flux vector's magnitude in the harmonic blend; c_iso = sqrt(T)
+ *   the unlimited one is their mean; the saturated flux takes q at the face
+ *   temperature (central) or, in the upwind form that Sec. 3 names without
+ *   giving it, at the temperature of the cell the classical face flux
+ *   leaves, with the full face flux vector's magnitude in the harmonic
+ *   blend either way; c_iso = sqrt(T)
  *   (p = rho T in code units); the stage operator is evaluated on each
  *   stage's own temperature and tau*M(Y0) is computed once and reused;
  *   boundaries are periodic.
@@ -51,7 +54,10 @@ typedef struct {
     int n[3];           /* cells per axis */
     double h[3];        /* cell widths */
     int limiter;        /* 0: mean of the four one-sided differences, 1: MC */
-    int saturation;     /* 0: classical flux only, 1: harmonic blend with q */
+    int saturation;     /* 0: classical flux only, 1: harmonic blend with q of
+                           the face temperature, 2: the same with q of the
+                           upwind cell (the upwind treatment of the
+                           saturated term named in Sec. 3) */
     double phi;         /* saturation uncertainty factor (Eq. Fsat) */
     double kappa0;      /* kappa_par = kappa0 * T^kappa_exp */
     double kappa_exp;
@@ -157,8 +163,13 @@ static double face_flux(const orc_grid *g, const double *T, const double *b,
     if (!g->saturation) return F[d];
 
     /* saturated flux q = 5 phi rho c_iso^3 with c_iso = sqrt(T), blended
-     * harmonically with the magnitude of the classical flux (Eq. Fc) */
-    const double t = Tf > 0.0 ? Tf : 0.0;
+     * harmonically with the magnitude of the classical flux (Eq. Fc).  T is
+     * the face temperature, or in the upwind form the temperature of the
+     * cell that the heat leaves through this face: L when the classical flux
+     * points from L to R (F_d > 0), else R. */
+    double Tq = Tf;
+    if (g->saturation == 2) Tq = F[d] > 0.0 ? TL : TR;
+    const double t = Tq > 0.0 ? Tq : 0.0;
     const double q = 5.0 * g->phi * g->rho * (t * sqrt(t));
     const double Fm = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
     if (q == 0.0) return 0.0;
