@@ -56,6 +56,10 @@ typedef enum {
 enum { RKL_FP64 = 0, RKL_MIXED = 1 };   /* flux arithmetic: FP64, or FP32 with FP64 stage recurrence */
 enum { RKL_RKL2 = 0, RKL_RKL1 = 1 };    /* super-step scheme: second- or first-order Legendre (Sec. 3.3) */
 enum { RKL_LIM_NONE = 0, RKL_LIM_MC = 1 };
+/* saturated flux: off; q at the face temperature (central); q at the
+ * temperature of the upwind cell, the one the classical face flux leaves
+ * (the upwind treatment of the saturated term that Sec. 3 names) */
+enum { RKL_SAT_NONE = 0, RKL_SAT_CENTRAL = 1, RKL_SAT_UPWIND = 2 };
 
 /* flag bits reported by rkl_query */
 enum {
@@ -71,7 +75,8 @@ typedef struct {
     double h[3];          /* cell widths, > 0 */
     int32_t limiter;      /* RKL_LIM_NONE: transverse gradient = mean of the four
                              one-sided differences; RKL_LIM_MC: MC(MC(a1,a2), MC(a3,a4)) */
-    int32_t saturation;   /* 0: classical flux; 1: blend q/(q+|F|) F (Eq. Fc) */
+    int32_t saturation;   /* RKL_SAT_NONE: classical flux; RKL_SAT_CENTRAL or
+                             RKL_SAT_UPWIND: blend q/(q+|F|) F (Eq. Fc) */
     double phi;           /* saturation factor of Eq. Fsat (0.3 in the paper) */
     double kappa0;        /* kappa_par = kappa0 * max(T,0)^kappa_exp, kappa0 >= 0 */
     double kappa_exp;     /* >= 0 (2.5 for Spitzer conduction) */

@@ -134,7 +134,7 @@ static bool validate(const rkl_grid_desc& g, std::string& why) {
     if ((int64_t)g.n[0] * g.n[1] > (int64_t)1 << 30 ||
         (int64_t)g.n[0] * g.n[1] * g.n[2] > ((int64_t)1 << 32)) { why = "grid too large"; return false; }
     if (g.limiter != RKL_LIM_NONE && g.limiter != RKL_LIM_MC) { why = "limiter must be RKL_LIM_NONE or RKL_LIM_MC"; return false; }
-    if (g.saturation != 0 && g.saturation != 1) { why = "saturation must be 0 or 1"; return false; }
+    if (g.saturation < 0 || g.saturation > 2) { why = "saturation must be 0, 1 or 2"; return false; }
     if (g.saturation && !(g.phi > 0.0 && std::isfinite(g.phi))) { why = "phi must be > 0"; return false; }
     if (!(g.kappa0 >= 0.0) || !std::isfinite(g.kappa0)) { why = "kappa0 must be finite and >= 0"; return false; }
     if (!(g.kappa_exp >= 0.0) || !std::isfinite(g.kappa_exp)) { why = "kappa_exp must be finite and >= 0"; return false; }

@@ -95,7 +95,7 @@ struct BatchBufs {
 };
 
 // stage j of tile t of grid g
-template <typename R, bool LIM, bool SAT, int KM, typename L_t>
+template <typename R, bool LIM, int SAT, int KM, typename L_t>
 __device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int t, const GridState& st,
                                            L_t& L) {
     const BatchGrid& G = P.grids[g];
@@ -150,7 +150,7 @@ __device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int
     run_tile<R, LIM, SAT, KM>(a, fk, tref, L);
 }
 
-template <typename R, bool LIM, bool SAT, int KM>
+template <typename R, bool LIM, int SAT, int KM>
 __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int2* __restrict__ items,
                                                           int stage) {
     __shared__ TileLds<R, kPL, kFX, kFY> L;
@@ -265,14 +265,18 @@ void batch_free(BatchPlan* bp) {
     delete bp;
 }
 
+template <typename R, bool LIM, int KM>
+static void launch_stage_sat(const BatchPlan* bp, const BatchBufs& a, int stage, hipStream_t st) {
+    const int2* it = bp->items_dev;
+    if (bp->saturation == 2) batch_stage_kernel<R, LIM, 2, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    else if (bp->saturation == 1) batch_stage_kernel<R, LIM, 1, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    else batch_stage_kernel<R, LIM, 0, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
+}
+
 template <typename R, int KM>
 static void launch_stage_km(const BatchPlan* bp, const BatchBufs& a, int stage, hipStream_t st) {
-    const bool lim = bp->limiter != 0, sat = bp->saturation != 0;
-    const int2* it = bp->items_dev;
-    if (lim && sat) batch_stage_kernel<R, true, true, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
-    else if (lim) batch_stage_kernel<R, true, false, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
-    else if (sat) batch_stage_kernel<R, false, true, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
-    else batch_stage_kernel<R, false, false, KM><<<bp->items, kBT, 0, st>>>(a, it, stage);
+    if (bp->limiter != 0) launch_stage_sat<R, true, KM>(bp, a, stage, st);
+    else launch_stage_sat<R, false, KM>(bp, a, stage, st);
 }
 
 template <typename R>

@@ -63,7 +63,7 @@ struct FusedLds {
     R FY2[2][RL];   // face between region cells c and c+BX
 };
 
-template <typename R, bool LIM, bool SAT, int KM, int BX, int BY>
+template <typename R, bool LIM, int SAT, int KM, int BX, int BY>
 __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& fk, double tref,
                                            FusedLds<R, BX, BY>& L) {
     using Lds = FusedLds<R, BX, BY>;

@@ -17,7 +17,7 @@ struct FusedLaunch {
     int kmode;
 };
 
-template <bool LIM, bool SAT, int KM, int BX, int BY>
+template <bool LIM, int SAT, int KM, int BX, int BY>
 __global__ __launch_bounds__(BX* BY) void fused2_kernel(FusedLaunch P) {
     __shared__ FusedLds<float, BX, BY> L;
     int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -44,16 +44,21 @@ __global__ __launch_bounds__(BX* BY) void fused2_kernel(FusedLaunch P) {
     run_fused2<float, LIM, SAT, KM, BX, BY>(a, fk, tref, L);
 }
 
+template <bool LIM, int KM, int BX, int BY>
+static void fused_sat(const FusedLaunch& P, int nblocks, int sat, hipStream_t st) {
+    if (sat == 2) fused2_kernel<LIM, 2, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    else if (sat == 1) fused2_kernel<LIM, 1, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+    else fused2_kernel<LIM, 0, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+}
+
 template <int KM, int BX, int BY>
-static void fused_km(const FusedLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
-    if (lim && sat) fused2_kernel<true, true, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (lim) fused2_kernel<true, false, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (sat) fused2_kernel<false, true, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
-    else fused2_kernel<false, false, KM, BX, BY><<<nblocks, BX * BY, 0, st>>>(P);
+static void fused_km(const FusedLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
+    if (lim) fused_sat<true, KM, BX, BY>(P, nblocks, sat, st);
+    else fused_sat<false, KM, BX, BY>(P, nblocks, sat, st);
 }
 
 template <int BX, int BY>
-static hipError_t fused_shape(const FusedLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
+static hipError_t fused_shape(const FusedLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
     if (P.kmode == 0) fused_km<0, BX, BY>(P, nblocks, lim, sat, st);
     else if (P.kmode == 1) fused_km<1, BX, BY>(P, nblocks, lim, sat, st);
     else fused_km<2, BX, BY>(P, nblocks, lim, sat, st);
@@ -98,7 +103,8 @@ hipError_t launch_fused2(Variant v, const GridConst& gc, int stage, const double
     P.kmode = gc.kmode;
     const int64_t nb = (int64_t)P.ntx * P.nty * nzc;
     if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
-    const bool lim = gc.limiter != 0, sat = gc.saturation != 0;
+    const bool lim = gc.limiter != 0;
+    const int sat = gc.saturation;
     if (v.bx == 16 && v.by == 16) return fused_shape<16, 16>(P, (int)nb, lim, sat, st);
     if (v.bx == 32 && v.by == 8) return fused_shape<32, 8>(P, (int)nb, lim, sat, st);
     return hipErrorInvalidValue;

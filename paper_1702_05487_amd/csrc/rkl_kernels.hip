@@ -106,7 +106,7 @@ struct StageLaunch {
 };
 
 // FIX3: 3-D grid, tile shape fixed at compile time (run_tile's CBX, CBY)
-template <typename R, bool LIM, bool SAT, int KM, int BX, int BY, bool FIX3>
+template <typename R, bool LIM, int SAT, int KM, int BX, int BY, bool FIX3>
 __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
     constexpr int PL = (BX + 2) * (BY + 2);
     __shared__ TileLds<R, PL, (BX + 1) * BY, BX*(BY + 1)> L;
@@ -148,22 +148,27 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
         run_tile<R, LIM, SAT, KM>(a, fk, tref, L);
 }
 
+template <typename R, bool LIM, int KM, int BX, int BY, bool FIX3>
+static void launch_sat(const StageLaunch& P, int nblocks, int sat, hipStream_t st) {
+    if (sat == 2) stage_kernel<R, LIM, 2, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
+    else if (sat == 1) stage_kernel<R, LIM, 1, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
+    else stage_kernel<R, LIM, 0, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
+}
+
 template <typename R, int KM, int BX, int BY, bool FIX3>
-static void launch_fix(const StageLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
-    if (lim && sat) stage_kernel<R, true, true, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (lim) stage_kernel<R, true, false, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (sat) stage_kernel<R, false, true, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
-    else stage_kernel<R, false, false, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
+static void launch_fix(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
+    if (lim) launch_sat<R, true, KM, BX, BY, FIX3>(P, nblocks, sat, st);
+    else launch_sat<R, false, KM, BX, BY, FIX3>(P, nblocks, sat, st);
 }
 
 template <typename R, int KM, int BX, int BY>
-static void launch_km(const StageLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
+static void launch_km(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
     if (P.t.ndim == 3) launch_fix<R, KM, BX, BY, true>(P, nblocks, lim, sat, st);
     else launch_fix<R, KM, BX, BY, false>(P, nblocks, lim, sat, st);
 }
 
 template <typename R, int BX, int BY>
-static hipError_t launch_shape(const StageLaunch& P, int nblocks, bool lim, bool sat, hipStream_t st) {
+static hipError_t launch_shape(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
     if (P.kmode == 0) launch_km<R, 0, BX, BY>(P, nblocks, lim, sat, st);
     else if (P.kmode == 1) launch_km<R, 1, BX, BY>(P, nblocks, lim, sat, st);
     else launch_km<R, 2, BX, BY>(P, nblocks, lim, sat, st);
@@ -171,7 +176,7 @@ static hipError_t launch_shape(const StageLaunch& P, int nblocks, bool lim, bool
 }
 
 template <typename R>
-static hipError_t launch_prec(const StageLaunch& P, int nblocks, int bx, int by, bool lim, bool sat,
+static hipError_t launch_prec(const StageLaunch& P, int nblocks, int bx, int by, bool lim, int sat,
                               hipStream_t st) {
     if (bx == 32 && by == 8) return launch_shape<R, 32, 8>(P, nblocks, lim, sat, st);
     if (bx == 64 && by == 4) return launch_shape<R, 64, 4>(P, nblocks, lim, sat, st);
@@ -221,7 +226,8 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
     P.sub_scale = sub_scale;
     const int64_t nb = (int64_t)P.ntx * P.nty * nzc;
     if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
-    const bool lim = gc.limiter != 0, sat = gc.saturation != 0;
+    const bool lim = gc.limiter != 0;
+    const int sat = gc.saturation;
     if (precision == RKL_MIXED) return launch_prec<float>(P, (int)nb, v.bx, v.by, lim, sat, st);
     return launch_prec<double>(P, (int)nb, v.bx, v.by, lim, sat, st);
 }

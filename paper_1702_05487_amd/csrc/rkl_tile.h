@@ -117,7 +117,9 @@ __device__ __forceinline__ FaceK<R> make_facek(double kappa0, double kexp, doubl
 }
 
 // Normal component of F_c through a face, for cells L (low) and R (high)
-// along the face normal.  s?1, s?2: the cells' slopes along the two
+// along the face normal.  SAT: 0 classical flux, 1 saturated blend with q at
+// the face temperature, 2 the same with q at the temperature of the upwind
+// cell, the one the classical flux -kappa_par A leaves (L when A < 0).  s?1, s?2: the cells' slopes along the two
 // transverse axes; b?n/b?1/b?2: the cells' unit vectors (normal, transverse
 // 1, transverse 2 components).  KM: conductivity law, 0 kappa0, 1 kappa0
 // T^2.5, 2 kappa0 T^kexp.
@@ -133,7 +135,7 @@ __device__ __forceinline__ FaceK<R> make_facek(double kappa0, double kexp, doubl
 // saturated flux 5 phi rho T^1.5 as satq T^2/sqrt(T) with the same T^1.5
 // (one reciprocal root; T is clipped at 1e-30 instead of 0 so that the root
 // stays finite, which changes kappa and q by less than 1e-75).
-template <typename R, bool LIM, bool SAT, int KM>
+template <typename R, bool LIM, int SAT, int KM>
 __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R sR2,
                                        R bLn, R bL1, R bL2, R bRn, R bR1, R bR2,
                                        const FaceK<R>& k) {
@@ -141,17 +143,23 @@ __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R
     const R G1 = face_transverse<R, LIM>(sL1, sR1);
     const R G2 = face_transverse<R, LIM>(sL2, sR2);
     const R Tf = fmax(fma(R(0.5), TL + TR, k.tref), R(1e-30));
-    const R t15 = (SAT || KM == 1) ? (Tf * Tf) * r_rsqrt(Tf) : R(0);   // T^1.5
+    const R t15 = (SAT == 1 || KM == 1) ? (Tf * Tf) * r_rsqrt(Tf) : R(0);   // T^1.5
     const R kpar = KM == 0 ? k.kappa0 : (KM == 1 ? k.kappa0 * (t15 * Tf) : k.kappa0 * r_pow(Tf, k.kexp));
     const R cn = bLn + bRn, c1 = bL1 + bR1, c2 = bL2 + bR2;
     const R cc = fma(cn, cn, fma(c1, c1, c2 * c2));
     const R cG = fma(cn, Gn, fma(c1, G1, c2 * G2));
     const R w = cc < R(1e-24) ? R(0) : cG * r_rcp(cc);     // (b.G)/|c|
     const R A = fma(k.r, Gn, k.omr * (cn * w));
-    if (!SAT) return -(kpar * A);
+    if (SAT == 0) return -(kpar * A);
     const R GG = fma(Gn, Gn, fma(G1, G1, G2 * G2));
     const R B2 = fma(k.r2, GG, k.omr2 * (cG * w));
-    const R q = k.satq * t15;
+    R q;
+    if (SAT == 2) {
+        const R Tu = fmax((A < R(0) ? TL : TR) + k.tref, R(1e-30));
+        q = k.satq * ((Tu * Tu) * r_rsqrt(Tu));
+    } else {
+        q = k.satq * t15;
+    }
     const R den = fma(kpar, r_sqrt(fmax(B2, R(0))), q);    // q + |F|
     return den > R(0) ? -(kpar * A) * (q * r_rcp(den)) : R(0);
 }
@@ -212,7 +220,7 @@ __device__ __forceinline__ double stage_combine(double mu, double nu, double omn
 // CBX, CBY > 0: the tile shape is a compile-time constant, the grid is 3-D
 // and the workgroup has exactly CBX*CBY threads (one cell each); the tile
 // strides are then constants and the face code has no runtime branches.
-template <typename R, bool LIM, bool SAT, int KM, int PLMAX, int FXMAX, int FYMAX, int CBX = 0, int CBY = 0>
+template <typename R, bool LIM, int SAT, int KM, int PLMAX, int FXMAX, int FYMAX, int CBX = 0, int CBY = 0>
 __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, double tref,
                                          TileLds<R, PLMAX, FXMAX, FYMAX>& L) {
     constexpr bool FIX = CBX > 0;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "librkl.so")
 RKL_OK, RKL_EINVAL, RKL_ENOMEM, RKL_EDEVICE, RKL_ESTAGES, RKL_ESTATE = range(6)
 RKL_FP64, RKL_MIXED = 0, 1
 RKL_LIM_NONE, RKL_LIM_MC = 0, 1
+RKL_SAT_NONE, RKL_SAT_CENTRAL, RKL_SAT_UPWIND = 0, 1, 2
 RKL_RKL2, RKL_RKL1 = 0, 1
 RKL_FLAG_NONPOS, RKL_FLAG_NONFINITE, RKL_FLAG_STAGES = 1, 2, 4
 
