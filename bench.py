@@ -30,6 +30,7 @@ WORKLOADS = {
     "spitzer_256_mixed": ("spitzer_256", "mixed"),
     "saturated_512": ("saturated_512", "mixed"),
     "saturated_512_fp64": ("saturated_512", "fp64"),
+    "saturated_512_upwind": ("saturated_512_upwind", "mixed"),
     "fused_768": ("fused_768", "mixed"),
     "patches_2000": ("patch_set", "mixed"),   # batched, graph-captured
     "spitzer_256_subcycle": ("spitzer_256", "fp64"),   # explicit sub-cycling over the same dt_hyp
@@ -212,7 +213,7 @@ def bench_batched(args, torch, inputs, rkl):
             "workload": "patches_2000", "patches": len(descs), "cells": int(cells.sum()),
             "stages_min": int(s1.min()), "stages_max": int(s1.max()), "precision": "mixed",
             "kappa_par": "T^2.5", "kperp_ratio": ps.params["kperp_ratio"], "limiter": "MC",
-            "saturation": False, "launch": "hipGraph replay, one launch per stage", "flags": int(flags),
+            "saturation": "off", "launch": "hipGraph replay, one launch per stage", "flags": int(flags),
             "tile_policy": policy, "policy_half_rows_tile_z": list(rkl.rkl_batch_policy_info(policy)),
             "autotuned_ms_per_step": tuned_ms,
         },
@@ -292,7 +293,7 @@ def bench_subcycle(args, torch, inputs, rkl):
         "config": {
             "workload": "tangled3d_256_fp64 explicit sub-cycling", "grid": list(w.n),
             "substeps_per_step": nsub // args.steps, "precision": "fp64", "kappa_par": "T^2.5",
-            "kperp_ratio": w.params["kperp_ratio"], "limiter": "MC", "saturation": False,
+            "kperp_ratio": w.params["kperp_ratio"], "limiter": "MC", "saturation": "off",
             "rkl2_stages_same_dt": stages // args.steps,
             "rkl2_ms_per_step": sec_sts * 1e3 / args.steps,
             "sts_speedup": sec_sub / sec_sts,
@@ -447,7 +448,8 @@ def main():
         "config": {
             "workload": w.name, "grid": list(w.n), "stages": s_last, "precision": precision,
             "kappa_par": "T^2.5", "kperp_ratio": w.params["kperp_ratio"],
-            "limiter": "MC" if w.params["limiter"] else "mean", "saturation": bool(w.params["saturation"]),
+            "limiter": "MC" if w.params["limiter"] else "mean",
+            "saturation": ["off", "central", "upwind"][w.params["saturation"]],
             "variant": variant, "tile": list(tile[:3]), "stages_per_launch": fuse,
             "autotuned_ms_per_step": tuned_ms,
         },

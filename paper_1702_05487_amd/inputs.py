@@ -198,6 +198,14 @@ def saturated_512(fields: bool = True, device=None) -> Workload:
     return tangled_3d(512, "mixed", True, 24, 10, fields=fields, device=device)
 
 
+def saturated_512_upwind(fields: bool = True, device=None) -> Workload:
+    """saturated_512 with the upwind saturated flux (q of the upwind cell)."""
+    w = tangled_3d(512, "mixed", True, 24, 10, fields=fields, device=device)
+    w.name += "_upwind"
+    w.params["saturation"] = 2
+    return w
+
+
 def fused_768(fields: bool = True, device=None) -> Workload:
     """768^3 mixed precision with saturation, s = 32, 20 super-steps."""
     return tangled_3d(768, "mixed", True, 32, 20, fields=fields, device=device)
