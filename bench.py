@@ -192,11 +192,22 @@ def bench_batched(args, torch, inputs, rkl):
     alg = 48.0 * float((cells * (s1 - 1)).sum())       # stage j >= 2 launches, 48 B per cell-stage
     achieved = alg / (ms / 1e3) / 1e9
     flags = max(plan.query(g)[2] for g in range(0, len(descs), 97))
+    sample = None
+    if not args.no_cpu_baseline:
+        # host copies of the first patches (about 2.5e7 cell-stages) and the
+        # library's result of the same super-step
+        npick, work = 0, 0
+        while npick < len(descs) and work < 2.5e7:
+            work += int(cells[npick] * s1[npick])
+            npick += 1
+        sample = [(ps.n[p], dts[p], int(s1[p]), T0[off[p]:off[p + 1]].cpu().numpy(),
+                   b[3 * off[p]:3 * off[p + 1]].double().cpu().numpy(), T[off[p]:off[p + 1]].cpu().numpy())
+                  for p in range(npick)]
     plan.close()
     del T, T0, b
     torch.cuda.empty_cache()
     ceil = copy_ceiling(torch)
-    return {
+    out = {
         "metric": "cell-stage updates/s",
         "value": cell_stages / sec,
         "unit": "cell-stage/s",
@@ -225,6 +236,40 @@ def bench_batched(args, torch, inputs, rkl):
             "copy_GBs": ceil, "frac_of_copy": achieved / ceil,
         },
     }
+    if sample is not None:
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline_patches(sample, ps.params)
+    return out
+
+
+def cpu_baseline_patches(sample, params):
+    """The oracle, untuned, on the first patches of the batched workload (one
+    super-step each, one host core), and the error of the library's batched
+    mixed-precision result for those patches against it."""
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    err = ref_sum = chg_sum = linf = 0.0
+    cs = 0
+    same_s = True
+    for n, dt, s_lib, T, bb, got in sample:
+        g = oracle.Grid(n=tuple(n), h=(1 / 64,) * 3, ndim=3, **params)
+        shape = (n[2], n[1], n[0])
+        T = T.reshape(shape)
+        ref, s, _ = oracle.superstep(g, T, bb.reshape((3,) + shape), dt)
+        got = got.reshape(shape)
+        err += float(np.abs(got - ref).sum())
+        ref_sum += float(np.abs(ref).sum())
+        chg_sum += float(np.abs(ref - T).sum())
+        linf = max(linf, float(np.abs(got - ref).max()))
+        same_s = same_s and s == s_lib
+        cs += int(np.prod(n)) * s
+    sec = time.perf_counter() - t0
+    base = {"value": cs / sec, "unit": "cell-stage/s", "cores": 1, "kind": "oracle",
+            "sample": "one super-step of the first %d patches (%d cell-stages, %.1f s serial)"
+                      % (len(sample), cs, sec)}
+    acc = {"rel_l1": err / ref_sum, "linf": linf, "rel_l1_change": err / chg_sum, "same_stage_counts": same_s,
+           "sample": "the same patches and super-step, library (mixed, batched) vs oracle (FP64)"}
+    return base, acc
 
 
 def bench_subcycle(args, torch, inputs, rkl):
