@@ -151,6 +151,9 @@ rkl_status rkl_dt_par(rkl_plan_t plan, int32_t grid, const double *T, double *dt
  * w1 tau M(Y_0), Y_j = (2j-1)/j (Y_{j-1} + w1 tau M(Y_{j-1})) - (j-1)/j Y_{j-2},
  * and s from dt_hyp = dt_par (s^2+s)/2 rounded as for RKL2 (s >= 1; s = 1 is
  * one forward-Euler step).
+ * For a super-step with no host synchronisation (HIP graph capture), use
+ * rkl_superstep_batched on a plan of one grid with smax near the expected s;
+ * it gives the same bits as this entry point.
  */
 rkl_status rkl_superstep(rkl_plan_t plan, int32_t grid, double *T, const void *b,
                          double dt_hyp, int32_t *s_out, void *stream);

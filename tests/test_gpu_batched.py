@@ -263,3 +263,40 @@ def test_batched_autotune(torch_cuda):
     with pytest.raises(rkl.RklError):
         plan.autotune_batched(T, b, dt, reps=0)
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_grid_graph_equals_superstep(torch_cuda, precision):
+    """A plan of one grid: rkl_superstep (host read-back of s), the batched
+    entry point and a captured graph of it replayed give the same bits, for
+    three consecutive super-steps."""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    n = (48, 40, 36)
+    h = tuple(1.0 / v for v in n)
+    p = dict(inputs.SPITZER_MC_SAT, phi=0.003)
+    T0 = inputs.noisy_temperature(n, 2, kmax=8)
+    b = inputs.tangled_b(n, 1, kmax=8)
+    bdt = torch.float32 if precision == "mixed" else torch.float64
+    bd = torch.from_numpy(b).to("cuda:0", dtype=bdt)
+    one = rkl.Plan([lib_desc(n, h, 3, p)], precision=precision)
+    bat = rkl.Plan([lib_desc(n, h, 3, p)], precision=precision, smax=24)
+    Ta = torch.from_numpy(T0).to("cuda:0")
+    Tb = Ta.clone()
+    Tg = Ta.clone()
+    dt = inputs.midpoint_ratio(14) * one.dt_par(Ta)
+    dtd = torch.tensor([dt], dtype=torch.float64, device="cuda:0")
+    s_out = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    graph = rkl.Plan([lib_desc(n, h, 3, p)], precision=precision, smax=24)
+    graph.graph_capture(Tg, bd, dtd, s_out)
+    for _ in range(3):
+        s = one.superstep(Ta, bd, dt)
+        bat.superstep_batched(Tb, bd, dtd, s_out)
+        assert int(s_out.item()) == s
+        graph.graph_launch()
+        torch.cuda.synchronize()
+        assert int(s_out.item()) == s
+        assert torch.equal(Ta, Tb)
+        assert torch.equal(Ta, Tg)
+    for pl in (one, bat, graph):
+        pl.close()
