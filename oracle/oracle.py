@@ -34,12 +34,14 @@ class _CGrid(ctypes.Structure):
         ("rho", ctypes.c_double),
         ("gamma", ctypes.c_double),
         ("cp", ctypes.c_double),
+        ("boundary", ctypes.c_int * 3),
     ]
 
 
 @dataclass
 class Grid:
-    """Periodic grid + conduction parameters (same meaning as in rkl_oracle.c)."""
+    """Grid + conduction parameters (same meaning as in rkl_oracle.c);
+    boundary[d] = 0 periodic, 1 outflow."""
     n: tuple                      # (n0, n1, n2), axis 0 fastest
     h: tuple = (1.0, 1.0, 1.0)
     ndim: int = 3
@@ -52,6 +54,7 @@ class Grid:
     rho: float = 1.0
     gamma: float = 2.0
     cp: float = 0.5
+    boundary: tuple = (0, 0, 0)
     _c: _CGrid = field(default=None, repr=False, compare=False)
 
     @property
@@ -73,6 +76,8 @@ class Grid:
         g.rho = float(self.rho)
         g.gamma = float(self.gamma)
         g.cp = float(self.cp)
+        for d in range(3):
+            g.boundary[d] = int(self.boundary[d])
         return g
 
 

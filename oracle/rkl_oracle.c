@@ -38,7 +38,9 @@
  *   blend either way; c_iso = sqrt(T)
  *   (p = rho T in code units); the stage operator is evaluated on each
  *   stage's own temperature and tau*M(Y0) is computed once and reused;
- *   boundaries are periodic.
+ *   each axis is periodic or outflow (ghost cells repeat the edge cell's T
+ *   and b, as in the exact-solution or outflow ghosts the paper's tests use
+ *   at non-periodic edges).
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math), so every
  * a*b+c rounds twice, exactly as written.
@@ -65,17 +67,24 @@ typedef struct {
     double rho;         /* frozen density */
     double gamma;       /* ratio of specific heats */
     double cp;          /* parabolic Courant number, <= 1/2 */
+    int boundary[3];    /* per axis: 0 periodic, 1 outflow (the cells beyond
+                           an edge repeat the edge cell: zero-gradient ghosts) */
 } orc_grid;
 
 static long ncell(const orc_grid *g) { return (long)g->n[0] * g->n[1] * g->n[2]; }
 
-/* periodic index of cell (c[0], c[1], c[2]) */
+/* index of cell (c[0], c[1], c[2]): wrapped on periodic axes, clamped to
+ * the edge cell on outflow axes */
 static long cell_index(const orc_grid *g, const int c[3])
 {
     int w[3];
     for (int d = 0; d < 3; ++d) {
-        int m = c[d] % g->n[d];
-        w[d] = m < 0 ? m + g->n[d] : m;
+        if (g->boundary[d]) {
+            w[d] = c[d] < 0 ? 0 : (c[d] >= g->n[d] ? g->n[d] - 1 : c[d]);
+        } else {
+            int m = c[d] % g->n[d];
+            w[d] = m < 0 ? m + g->n[d] : m;
+        }
     }
     return ((long)w[2] * g->n[1] + w[1]) * g->n[0] + w[0];
 }
