@@ -9,7 +9,7 @@
  * The library evolves a cell-centred temperature T under the operator-split
  * conduction equation d(rho eps)/dt = -div F_c (Sec. 3, Eq. scalar_diffusion)
  * with rho eps = rho T/(gamma-1), i.e. dT/dt = (gamma-1)/rho (-div F_c),
- * on periodic Cartesian grids.  F_c is the harmonic blend of the classical
+ * on Cartesian grids whose axes are periodic or outflow.  F_c is the harmonic blend of the classical
  * field-aligned flux -kappa_par b (b.grad T) (plus an optional
  * -kappa_perp (grad T - b (b.grad T)) term) and the saturated flux
  * q = 5 phi rho c_iso^3 (Sec. 2, Eqs. Fc, Fclass, Fsat), discretised with
@@ -60,6 +60,10 @@ enum { RKL_LIM_NONE = 0, RKL_LIM_MC = 1 };
  * temperature of the upwind cell, the one the classical face flux leaves
  * (the upwind treatment of the saturated term that Sec. 3 names) */
 enum { RKL_SAT_NONE = 0, RKL_SAT_CENTRAL = 1, RKL_SAT_UPWIND = 2 };
+/* per-axis boundary: periodic, or outflow (the cells beyond an edge repeat
+ * the edge cell's T and b at every stage: zero-gradient ghost cells, the
+ * non-periodic edges of the paper's tests) */
+enum { RKL_BC_PERIODIC = 0, RKL_BC_OUTFLOW = 1 };
 
 /* flag bits reported by rkl_query */
 enum {
@@ -84,6 +88,8 @@ typedef struct {
     double rho;           /* frozen density, > 0 */
     double gamma;         /* ratio of specific heats, > 1 */
     double cp;            /* parabolic Courant number of Eq. dt_exp, in (0, 1/2] */
+    int32_t boundary[3];  /* per axis: RKL_BC_PERIODIC (0, the default of a
+                             zeroed descriptor) or RKL_BC_OUTFLOW */
 } rkl_grid_desc;
 
 typedef struct {
@@ -227,7 +233,7 @@ rkl_status rkl_query(rkl_plan_t plan, int32_t grid, int32_t *last_s, double *las
  *   fuse 2: stages j and j+1 in one launch (temporal fusion of Appendix A's
  *           recurrence; 2 <= j, j+1 < s, the last stage always runs alone),
  *           output tile (tile_x-2) x (tile_y-2): the tile's border ring is
- *           recomputed by the neighbouring tiles.  RKL_MIXED plans of 3-D
+ *           recomputed by the neighbouring tiles.  RKL_MIXED plans of periodic 3-D
  *           grids only; selecting one allocates two more FP64 stage buffers.
  * rkl_set_variant selects a variant for a plan (RKL_EINVAL if the plan
  * cannot use it, RKL_ENOMEM); the autotuner calls it.

@@ -142,6 +142,12 @@ static bool validate(const rkl_grid_desc& g, std::string& why) {
     if (!(g.rho > 0.0) || !std::isfinite(g.rho)) { why = "rho must be finite and > 0"; return false; }
     if (!(g.gamma > 1.0) || !std::isfinite(g.gamma)) { why = "gamma must be finite and > 1"; return false; }
     if (!(g.cp > 0.0 && g.cp <= 0.5)) { why = "cp must be in (0, 1/2]"; return false; }
+    for (int d = 0; d < 3; ++d)
+        if (g.boundary[d] != RKL_BC_PERIODIC && g.boundary[d] != RKL_BC_OUTFLOW) {
+            snprintf(buf, sizeof buf, "boundary[%d] must be RKL_BC_PERIODIC or RKL_BC_OUTFLOW", d);
+            why = buf;
+            return false;
+        }
     return true;
 }
 
@@ -162,6 +168,7 @@ static GridConst make_const(const rkl_grid_desc& g, int scheme) {
     c.limiter = g.limiter;
     c.saturation = g.saturation;
     c.scheme = scheme;
+    c.bc = (g.boundary[0] ? 1 : 0) | (g.boundary[1] ? 2 : 0) | (g.boundary[2] ? 4 : 0);
     c.fac = (g.gamma - 1.0) / g.rho;
     c.cp = g.cp;
     double s = 0.0;
@@ -295,19 +302,19 @@ rkl_status rkl_variant_info(int32_t v, int32_t* tx, int32_t* ty, int32_t* tz, in
     return RKL_OK;
 }
 
-// A two-stage variant needs RKL_MIXED and 3-D grids, and two more stage
-// buffers (tiles overlap, so its outputs may not overwrite its inputs).
+// A two-stage variant needs RKL_MIXED and periodic 3-D grids, and two more
+// stage buffers (tiles overlap, so its outputs may not overwrite its inputs).
 static bool fused_ok(const rkl_plan_s* p) {
     if (p->precision != RKL_MIXED) return false;
     for (const auto& d : p->desc)
-        if (d.ndim != 3) return false;
+        if (d.ndim != 3 || d.boundary[0] || d.boundary[1] || d.boundary[2]) return false;
     return true;
 }
 
 static rkl_status select_variant(rkl_plan_s* p, int v) {
     const Variant x = variant_get(v);
     if (x.fuse == 2) {
-        if (!fused_ok(p)) return fail(RKL_EINVAL, "two-stage variants need an RKL_MIXED plan of 3-D grids");
+        if (!fused_ok(p)) return fail(RKL_EINVAL, "two-stage variants need an RKL_MIXED plan of periodic 3-D grids");
         if (!p->Yc) {
             if (hipMalloc(&p->Yc, sizeof(double) * p->total) != hipSuccess ||
                 hipMalloc(&p->Yd, sizeof(double) * p->total) != hipSuccess) {

@@ -114,6 +114,7 @@ __device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int
     a.n1 = G.gc.n1;
     a.n2 = G.gc.n2;
     a.ndim = G.gc.ndim;
+    a.bc = G.gc.bc;
     a.bx = G.bx;
     a.by = G.by;
     a.x0 = tile_x * G.bx;

@@ -25,6 +25,7 @@ struct GridConst {
     int kmode;              // 0: kappa0, 1: kappa0 T^2.5, 2: kappa0 T^kexp
     int limiter, saturation;
     int scheme;             // 0 RKL2, 1 RKL1
+    int bc;                 // bit d set: axis d is outflow, else periodic
     double fac;             // (gamma-1)/rho
     double cp, ihsum;       // Courant number, sum_d 1/h_d^2 over active axes
 };

@@ -205,6 +205,7 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
     a.bx = v.bx;
     a.by = v.by;
     a.kind = kind;
+    a.bc = gc.bc;
     a.ih0 = gc.ih0;
     a.ih1 = gc.ih1;
     a.ih2 = gc.ih2;

@@ -177,6 +177,7 @@ struct TileArgs {
     int x0, y0, z0, z1;  // tile origin and z range [z0, z1)
     int bx, by;          // tile shape (bx*by <= threads, 2bx+2by+4 <= threads)
     int kind;
+    int bc;              // bit d set: axis d is outflow, else periodic
     double ih0, ih1, ih2;
     double scale;        // multiplies div F: -(gamma-1)/rho (kind 0) or -tau (gamma-1)/rho
     double mu, nu, omn, mut, gt;
@@ -203,6 +204,12 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 __device__ __forceinline__ int wrap(int i, int n) {
     int m = i % n;
     return m < 0 ? m + n : m;
+}
+
+// index of cell i along an axis of n cells: wrapped (periodic axis) or
+// clamped to the edge cell (outflow axis: the cells beyond an edge repeat it)
+__device__ __forceinline__ int bidx(int i, int n, bool open) {
+    return open ? min(max(i, 0), n - 1) : wrap(i, n);
 }
 
 template <typename R>
@@ -237,12 +244,13 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     const R ih0 = R(a.ih0), ih1 = R(a.ih1), ih2 = R(a.ih2);
     const R hih0 = R(0.5 * a.ih0), hih1 = R(0.5 * a.ih1), hih2 = R(0.5 * a.ih2);
     const bool do_y = FIX || a.ndim >= 2, do_z = FIX || a.ndim >= 3;
+    const bool ox = a.bc & 1, oy = a.bc & 2, oz = a.bc & 4;
 
     // own cell of this thread
     const bool own = FIX || tid < bx * by;
     const int tx = own ? tid % bx : 0, ty = own ? tid / bx : 0;
     const int oslot = (ty + 1) * px + tx + 1;
-    const int oxy = wrap(a.y0 + ty, n1) * n0 + wrap(a.x0 + tx, n0);
+    const int oxy = bidx(a.y0 + ty, n1, oy) * n0 + bidx(a.x0 + tx, n0, ox);
     const bool store = own && (a.x0 + tx < n0) && (a.y0 + ty < n1);
 
     // halo cell of this thread: the 2bx+2by edge cells first (y-halo rows,
@@ -266,7 +274,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
             hj = (c & 2) ? by : -1;
         }
         hslot = (hj + 1) * px + hi + 1;
-        hxy = wrap(a.y0 + hj, n1) * n0 + wrap(a.x0 + hi, n0);
+        hxy = bidx(a.y0 + hj, n1, oy) * n0 + bidx(a.x0 + hi, n0, ox);
     }
     // extra face: the tile's -x face of row j (f < by) or -y face of column i.
     // These jobs go to the last wave(s) of the workgroup while the halo jobs
@@ -283,8 +291,8 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     }
 
     const int z0 = a.z0, z1 = a.z1;
-    // wrapped index of plane k + 4, the temperature plane prefetched at plane k
-    int pz4 = wrap(z0 + 2, n2);
+    // index of plane k + 4, the temperature plane prefetched at plane k
+    int pz4 = bidx(z0 + 2, n2, oz);
 
     // Prefetch pipeline, two planes deep: set 0 is stored into LDS at this
     // plane's step A, set 1 at the next plane's.  Values stay in their loaded
@@ -312,12 +320,12 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     // ring slots: T(k) c0, T(k+1) c1, T(k+2) c2; slopes/b of plane k in dc, of k+1 in dn
     int c0 = 0, c1 = 1, c2 = 2, dc = 1, dn = 0, fb = 0;
     {
-        const double* p0 = a.Yin + (size_t)wrap(z0 - 2, n2) * plane;
-        const double* p1 = a.Yin + (size_t)wrap(z0 - 1, n2) * plane;
-        const double* p2 = a.Yin + (size_t)wrap(z0, n2) * plane;
-        const double* p3 = a.Yin + (size_t)wrap(z0 + 1, n2) * plane;
-        const size_t pb0 = (size_t)wrap(z0 - 1, n2) * plane;
-        const size_t pb1 = (size_t)wrap(z0, n2) * plane;
+        const double* p0 = a.Yin + (size_t)bidx(z0 - 2, n2, oz) * plane;
+        const double* p1 = a.Yin + (size_t)bidx(z0 - 1, n2, oz) * plane;
+        const double* p2 = a.Yin + (size_t)bidx(z0, n2, oz) * plane;
+        const double* p3 = a.Yin + (size_t)bidx(z0 + 1, n2, oz) * plane;
+        const size_t pb0 = (size_t)bidx(z0 - 1, n2, oz) * plane;
+        const size_t pb1 = (size_t)bidx(z0, n2, oz) * plane;
         if (own) {
             yq1 = p0[oxy];
             yq2 = p1[oxy];
@@ -369,7 +377,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
         // prefetch two planes ahead: T(k+4) and b(k+3), used at plane k+2
         if (k + 2 < z1) {
             const double* pt = a.Yin + (size_t)pz4 * plane;
-            const int pbz = pz4 == 0 ? n2 - 1 : pz4 - 1;
+            const int pbz = oz ? min(k + 3, n2 - 1) : (pz4 == 0 ? n2 - 1 : pz4 - 1);
             const size_t pb = (size_t)pbz * plane;
             if (own) {
                 pTo1 = pt[oxy];
@@ -377,7 +385,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
             }
             if (hjob) pTh1 = pt[hxy];
             if (djob) { pbd10 = b0[pb + hxy]; pbd11 = b1[pb + hxy]; pbd12 = b2[pb + hxy]; }
-            pz4 = pz4 + 1 == n2 ? 0 : pz4 + 1;
+            pz4 = oz ? min(k + 5, n2 - 1) : (pz4 + 1 == n2 ? 0 : pz4 + 1);
         }
         ym2 = q1ym2; y0v = q1y0; my0 = q1my0;
         q1ym2 = q2ym2; q1y0 = q2y0; q1my0 = q2my0;

@@ -19,6 +19,7 @@ RKL_OK, RKL_EINVAL, RKL_ENOMEM, RKL_EDEVICE, RKL_ESTAGES, RKL_ESTATE = range(6)
 RKL_FP64, RKL_MIXED = 0, 1
 RKL_LIM_NONE, RKL_LIM_MC = 0, 1
 RKL_SAT_NONE, RKL_SAT_CENTRAL, RKL_SAT_UPWIND = 0, 1, 2
+RKL_BC_PERIODIC, RKL_BC_OUTFLOW = 0, 1
 RKL_RKL2, RKL_RKL1 = 0, 1
 RKL_FLAG_NONPOS, RKL_FLAG_NONFINITE, RKL_FLAG_STAGES = 1, 2, 4
 
@@ -46,6 +47,7 @@ class rkl_grid_desc(ctypes.Structure):
         ("rho", ctypes.c_double),
         ("gamma", ctypes.c_double),
         ("cp", ctypes.c_double),
+        ("boundary", ctypes.c_int32 * 3),
     ]
 
 
@@ -241,12 +243,13 @@ def rkl_profile_read(plan, fuse=1):
 
 # ------------------------------------------------------- torch wrapper ----
 def grid_desc(n, h, ndim=3, limiter=0, saturation=0, phi=0.3, kappa0=1.0, kappa_exp=0.0,
-              kperp_ratio=0.0, rho=1.0, gamma=2.0, cp=0.5):
+              kperp_ratio=0.0, rho=1.0, gamma=2.0, cp=0.5, boundary=(0, 0, 0)):
     d = rkl_grid_desc()
     d.ndim = int(ndim)
     for i in range(3):
         d.n[i] = int(n[i])
         d.h[i] = float(h[i])
+        d.boundary[i] = int(boundary[i])
     d.limiter, d.saturation = int(limiter), int(saturation)
     d.phi, d.kappa0, d.kappa_exp = float(phi), float(kappa0), float(kappa_exp)
     d.kperp_ratio, d.rho, d.gamma, d.cp = float(kperp_ratio), float(rho), float(gamma), float(cp)

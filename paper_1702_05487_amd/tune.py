@@ -1,8 +1,9 @@
 """Autotuner front end: picks the stencil kernel variant (tile shape and
 z-chunk length) for a grid by timing every variant on the caller's own
 fields (``rkl_autotune`` in librkl), and remembers the choice in a JSON cache
-keyed by everything that changes the kernel's cost: device name, grid shape,
-flux precision, limiter, saturation and conductivity law.
+keyed by everything that changes the kernel's cost or the variants a plan
+may use: device name, grid shape, flux precision, limiter, saturation form,
+conductivity law and boundaries.
 
 Cache file: $RKL_TUNE_CACHE, else ~/.cache/rkl/tune.json.  Writes are atomic
 (temp file + rename); a corrupt or unreadable cache is ignored.
@@ -49,8 +50,8 @@ def key(plan, grid):
     return "|".join(str(x) for x in (
         torch.cuda.get_device_name(0), tuple(d.n), d.ndim,
         "mixed" if plan.precision == rkl.RKL_MIXED else "fp64",
-        "mc" if d.limiter else "mean", "sat" if d.saturation else "nosat", kind,
-        rkl.rkl_variant_count()))
+        "mc" if d.limiter else "mean", ("nosat", "sat", "upwind")[d.saturation], kind,
+        "bc%d%d%d" % tuple(d.boundary), rkl.rkl_variant_count()))
 
 
 def autotune(plan, T, b, dt_hyp, reps=2, grid=0, cache=None):

@@ -49,6 +49,7 @@ def test_descriptor_struct_matches_header(tmp_path):
     dict(ndim=4), dict(n=(0, 4, 4)), dict(n=(4, 4, 2), ndim=2), dict(h=(0.0, 1, 1)),
     dict(limiter=2), dict(saturation=1, phi=0.0), dict(saturation=2, phi=0.0), dict(saturation=3),
     dict(saturation=-1), dict(kappa0=-1.0), dict(kappa_exp=-0.5),
+    dict(boundary=(2, 0, 0)), dict(boundary=(0, -1, 0)),
     dict(kperp_ratio=1.5), dict(rho=0.0), dict(gamma=1.0), dict(cp=0.6), dict(cp=0.0),
 ])
 def test_invalid_descriptors_are_rejected(bad):
