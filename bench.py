@@ -266,7 +266,7 @@ def cpu_baseline_patches(sample, params):
     sec = time.perf_counter() - t0
     base = {"value": cs / sec, "unit": "cell-stage/s", "cores": 1, "kind": "oracle",
             "sample": "one super-step of the first %d patches (%d cell-stages, %.1f s serial)"
-                      % (len(sample), cs, sec)}
+                      % (len(sample), cs, sec), "host": host_cpu()}
     acc = {"rel_l1": err / ref_sum, "linf": linf, "rel_l1_change": err / chg_sum, "same_stage_counts": same_s,
            "sample": "the same patches and super-step, library (mixed, batched) vs oracle (FP64)"}
     return base, acc
@@ -357,6 +357,19 @@ def bench_subcycle(args, torch, inputs, rkl):
     }
 
 
+def host_cpu():
+    """CPU model and the number of hardware threads visible to this process"""
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return "%s, %d threads visible" % (model, len(os.sched_getaffinity(0)))
+
+
 def cpu_baseline(w, T0, b, dt, precision, torch, rkl):
     """The oracle, untuned, on a bounded sample of the same workload: one
     super-step of length dt of a 256 x 256 x 16 periodic slab cut from the
@@ -376,7 +389,7 @@ def cpu_baseline(w, T0, b, dt, precision, torch, rkl):
     cells = m * m * nz
     base = {"value": cells * s / sec, "unit": "cell-stage/s", "cores": 1, "kind": "oracle",
             "sample": "one %d-stage super-step of a %dx%dx%d periodic slab cut from the same fields "
-                      "(%.1f s serial)" % (s, m, m, nz, sec)}
+                      "(%.1f s serial)" % (s, m, m, nz, sec), "host": host_cpu()}
     plan = rkl.Plan([rkl.grid_desc((m, m, nz), w.h, ndim=3, **w.params)], precision=precision)
     Td = torch.from_numpy(T).to("cuda:0")
     bd = torch.from_numpy(b).to("cuda:0", dtype=torch.float32 if precision == "mixed" else torch.float64)
