@@ -9,10 +9,12 @@
  * The library evolves a cell-centred temperature T under the operator-split
  * conduction equation d(rho eps)/dt = -div F_c (Sec. 3, Eq. scalar_diffusion)
  * with rho eps = rho T/(gamma-1), i.e. dT/dt = (gamma-1)/rho (-div F_c),
- * on Cartesian grids whose axes are periodic or outflow.  F_c is the harmonic blend of the classical
- * field-aligned flux -kappa_par b (b.grad T) (plus an optional
- * -kappa_perp (grad T - b (b.grad T)) term) and the saturated flux
- * q = 5 phi rho c_iso^3 (Sec. 2, Eqs. Fc, Fclass, Fsat), discretised with
+ * on Cartesian grids whose axes are periodic or outflow.  F_c is the
+ * harmonic blend of the classical field-aligned flux -kappa_par b (b.grad T)
+ * (plus an optional -kappa_perp (grad T - b (b.grad T)) term) and the
+ * saturated flux q = 5 phi rho c_iso^3 (Sec. 2, Eqs. Fc, Fclass, Fsat; q at
+ * the face temperature or, upwinded as Sec. 3 says, at the temperature of the
+ * cell the heat leaves), discretised with
  * the conservative second-order face differences of Sec. 3 and, optionally,
  * monotonized-central limited transverse gradients (Sec. 3.4, Appendix B).
  * A super-step of length dt_hyp takes s RKL2 stages (Appendix A, Eq.
@@ -72,7 +74,7 @@ enum {
     RKL_FLAG_STAGES = 4u      /* the stage count exceeded smax; that grid was not advanced */
 };
 
-/* One periodic grid and its conduction parameters. */
+/* One grid and its conduction parameters. */
 typedef struct {
     int32_t ndim;         /* 1, 2 or 3; n[d] must be 1 for d >= ndim */
     int32_t n[3];         /* cells along axes 0, 1, 2 (axis 0 fastest in memory) */

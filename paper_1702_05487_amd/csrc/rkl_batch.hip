@@ -1,4 +1,4 @@
-// rkl_batch.hip -- one RKL2 super-step of many independent periodic grids
+// rkl_batch.hip -- one RKL2 super-step of many independent grids
 // ("patches") of uneven size, each with its own field, super-step and stage
 // count, without host synchronisation (graph-capturable).
 //

@@ -14,9 +14,10 @@
 //
 // Layout: fields are [n2][n1][n0] (axis 0 fastest); b is 3 such arrays.
 // Scheme: a workgroup owns a bx x by column tile and marches along z.  Three
-// z planes of the stencil input (with a one-cell x/y halo, periodic wrap) sit
-// in an LDS ring; per-cell slopes and b of the current and next plane sit in
-// a two-plane LDS ring.  Every face flux is computed exactly once: each cell
+// z planes of the stencil input (with a one-cell x/y halo: wrapped on
+// periodic axes, the edge cell repeated on outflow axes) sit in an LDS ring;
+// per-cell slopes and b of the current and next plane sit in a two-plane LDS
+// ring.  Every face flux is computed exactly once: each cell
 // computes its +x, +y and +z faces, the tile's -x and -y boundary faces are
 // extra jobs, x/y faces are exchanged through (double-buffered) LDS and the
 // +z face is carried in a register to the next plane.  Each thread keeps the
