@@ -286,3 +286,33 @@ def test_saturated_512_sampled_full_size(torch_cuda):
         assert np.abs(got - ref).max() <= 4e-5
         assert rel_l1(got - t0, ref - t0) <= 1e-2
     plan.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_current_sheets(torch_cuda, precision, tol):
+    """b flips sign between random neighbouring cells (b_L + b_R = 0 on
+    many faces: the face direction vanishes and only kappa_perp conducts
+    there), 3D, Spitzer + MC + saturation, against the oracle"""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    n = (33, 21, 18)
+    h = (0.03, 0.04, 0.05)
+    rng = np.random.default_rng(41)
+    u = inputs.unit_vectors(rng.standard_normal((3, 1, 1, 1)) * np.ones((3,) + (n[2], n[1], n[0])))
+    b = u * np.where(rng.random((n[2], n[1], n[0])) < 0.5, 1.0, -1.0)[None]
+    T = inputs.noisy_temperature(n, 9, kmax=5)
+    p = dict(inputs.SPITZER_MC_SAT, phi=0.01, kperp_ratio=0.05)
+    bg = b.astype(np.float32) if precision == "mixed" else b
+    g = oracle_grid(n, h, 3, p)
+    plan = rkl.Plan([lib_desc(n, h, 3, p)], precision=precision)
+    bd = to_dev(torch, bg, torch.float32 if precision == "mixed" else torch.float64)
+    out = plan.flux_div(to_dev(torch, T, torch.float64), bd).cpu().numpy()
+    ref = oracle.flux_div(g, T, bg.astype(np.float64))
+    assert rel_l1(out, ref) <= tol
+    dt = inputs.midpoint_ratio(8) * oracle.dt_par(g, T)
+    Td = to_dev(torch, T, torch.float64)
+    s = plan.superstep(Td, bd, dt)
+    To, s_ref, _ = oracle.superstep(g, T, bg.astype(np.float64), dt)
+    plan.close()
+    assert s == s_ref == 8
+    assert rel_l1(Td.cpu().numpy(), To) <= tol

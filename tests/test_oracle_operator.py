@@ -220,3 +220,20 @@ def test_dt_par_is_the_explicit_stability_limit():
     assert oracle.dt_par(g2, T2) == pytest.approx(0.5 / lam, rel=1e-14)
     # zero conductivity: no parabolic limit
     assert np.isinf(oracle.dt_par(oracle.Grid(n=n, h=h, kappa0=0.0), T2))
+
+
+@pytest.mark.parametrize("r", [0.0, 0.1])
+def test_reversing_field_only_conducts_across(r):
+    """b = +x and -x in alternate cells (a current sheet at every face): the
+    face direction b_L + b_R vanishes, so only the perpendicular part
+    kappa_perp = r kappa crosses the faces -- the divergence is r times the
+    three-point Laplacian, and zero when kappa_perp = 0."""
+    N, h, kap = 32, 0.05, 2.0
+    rng = np.random.default_rng(5)
+    T = 1.0 + rng.random(N)
+    b = np.zeros((3, 1, 1, N))
+    b[0, 0, 0] = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    g = oracle.Grid(n=(N, 1, 1), h=(h, 1.0, 1.0), ndim=1, kappa0=kap, kperp_ratio=r)
+    out = oracle.flux_div(g, T[None, None], b).ravel()
+    lap = r * kap * (np.roll(T, -1) - 2 * T + np.roll(T, 1)) / h ** 2
+    assert np.abs(out - lap).max() <= 1e-12 * max(1.0, np.abs(lap).max())
