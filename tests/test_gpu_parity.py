@@ -316,3 +316,42 @@ def test_current_sheets(torch_cuda, precision, tol):
     plan.close()
     assert s == s_ref == 8
     assert rel_l1(Td.cpu().numpy(), To) <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_degenerate_inputs(torch_cuda, precision):
+    """no conduction (kappa0 = 0: dt_par is infinite, s = 2), a uniform
+    temperature (every gradient zero), single-cell grids in 1, 2 and 3
+    dimensions, and dt_hyp = 0: stage counts and results as the oracle's,
+    the flux divergence exactly zero where no heat can flow"""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    bt = torch.float32 if precision == "mixed" else torch.float64
+    rng = np.random.default_rng(43)
+    cases = []
+    n = (20, 12, 9)
+    b = inputs.unit_vectors(rng.standard_normal((3, 9, 12, 20)))
+    cases.append(("kappa0=0", n, 3, dict(inputs.SPITZER_MC_SAT, kappa0=0.0), 1.0 + rng.random((9, 12, 20)), b, 1e-3, True))
+    cases.append(("uniform T", n, 3, dict(inputs.SPITZER_MC_SAT), np.full((9, 12, 20), 1.7), b, 1e-4, True))
+    for nd, nn in ((1, (1, 1, 1)), (2, (1, 1, 1)), (3, (1, 1, 1))):
+        cases.append(("one cell %dD" % nd, nn, nd, dict(inputs.SPITZER_MC_SAT), np.full((1, 1, 1), 1.3),
+                      inputs.unit_vectors(rng.standard_normal((3, 1, 1, 1))), 1e-3, True))
+    cases.append(("dt_hyp=0", n, 3, dict(inputs.SPITZER_MC), 1.0 + rng.random((9, 12, 20)), b, 0.0, False))
+    for name, n, nd, p, T, b, dt, zero_div in cases:
+        h = (0.1, 0.2, 0.3)
+        bg = b.astype(np.float32) if precision == "mixed" else b
+        g = oracle_grid(n, h, nd, p)
+        plan = rkl.Plan([lib_desc(n, h, nd, p)], precision=precision)
+        bd = to_dev(torch, bg, bt)
+        div = plan.flux_div(to_dev(torch, T, torch.float64), bd).cpu().numpy()
+        if zero_div:
+            assert np.all(div == 0.0), name
+        Td = to_dev(torch, T, torch.float64)
+        s = plan.superstep(Td, bd, dt)
+        To, s_ref, _ = oracle.superstep(g, T, bg.astype(np.float64), dt)
+        plan.close()
+        print("%-10s s=%d rel-L1 %.2e" % (name, s, rel_l1(Td.cpu().numpy(), To)), flush=True)
+        assert s == s_ref == 2, name
+        assert rel_l1(Td.cpu().numpy(), To) <= tol, name
+        assert np.abs(Td.cpu().numpy() - T).max() <= 1e-14 * np.abs(T).max(), name
