@@ -355,3 +355,48 @@ def test_degenerate_inputs(torch_cuda, precision):
         assert s == s_ref == 2, name
         assert rel_l1(Td.cpu().numpy(), To) <= tol, name
         assert np.abs(Td.cpu().numpy() - T).max() <= 1e-14 * np.abs(T).max(), name
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_kernel_symmetries(torch_cuda, precision, tol):
+    """The library against itself: x and z faces run different code (LDS
+    exchange vs the register-carried z face), so exchanging axes x and z, or
+    reflecting y, must transform the flux divergence and the super-step
+    accordingly (up to the order of the three direction sums)."""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    from test_oracle_symmetry import reflect, swap
+    n, h = (37, 23, 29), (0.03, 0.04, 0.05)
+    p = dict(inputs.SPITZER_MC_SAT, phi=0.01, kperp_ratio=0.05)
+    T = inputs.noisy_temperature(n, 12, amp=0.3, kmax=4)
+    b = inputs.tangled_b(n, 13, kmax=4)
+    bt = torch.float32 if precision == "mixed" else torch.float64
+    if precision == "mixed":
+        b = b.astype(np.float32).astype(np.float64)
+
+    def run(n_, h_, T_, b_, dt=None):
+        plan = rkl.Plan([lib_desc(n_, h_, 3, p)], precision=precision)
+        Td = to_dev(torch, T_, torch.float64)
+        bd = to_dev(torch, b_, bt)
+        div = plan.flux_div(Td, bd).cpu().numpy()
+        s = plan.superstep(Td, bd, dt) if dt else 0
+        out = Td.cpu().numpy()
+        plan.close()
+        return div, out, s
+
+    dt = inputs.midpoint_ratio(9) * oracle.dt_par(oracle_grid(n, h, 3, p), T)
+    div0, out0, s0 = run(n, h, T, b, dt)
+    T2, b2, h2, n2, perm = swap(T, b, h, n, 0, 2)
+    div1, out1, s1 = run(n2, h2, T2, b2, dt)
+    T3, b3 = reflect(T, b, 1)
+    div2, out2, s2 = run(n, h, T3, b3, dt)
+    assert s0 == s1 == s2 == 9
+    scale, chg = np.abs(div0).max(), np.abs(out0 - T).max()
+    gaps = [np.abs(np.transpose(div1, perm) - div0).max() / scale,
+            np.abs(np.flip(div2, axis=1) - div0).max() / scale,
+            np.abs(np.transpose(out1, perm) - out0).max() / chg,
+            np.abs(np.flip(out2, axis=1) - out0).max() / chg]
+    print(precision, "relative gaps (div x<->z, div y-mirror, step x<->z, step y-mirror):",
+          " ".join("%.1e" % v for v in gaps))
+    # mixed: the three FP32 direction sums are added in another order
+    assert max(gaps) <= tol
