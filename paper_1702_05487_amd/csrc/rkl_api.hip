@@ -67,8 +67,8 @@ struct rkl_plan_s {
 
 static void prof_clear(rkl_plan_s* p) {
     for (auto& r : p->prof_recs) {
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
     }
     p->prof_recs.clear();
 }
@@ -180,19 +180,19 @@ static GridConst make_const(const rkl_grid_desc& g, int scheme) {
 static void free_plan(rkl_plan_s* p) {
     if (!p) return;
     prof_clear(p);
-    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     batch_free(p->batch);
-    hipFree(p->Ya);
-    hipFree(p->Yb);
-    hipFree(p->Yc);
-    hipFree(p->Yd);
-    hipFree(p->MY0);
-    hipFree(p->coef);
-    hipFree(p->state);
-    hipFree(p->partials);
-    hipFree(p->s_dev);
-    if (p->s_host) hipHostFree(p->s_host);
+    (void)hipFree(p->Ya);
+    (void)hipFree(p->Yb);
+    (void)hipFree(p->Yc);
+    (void)hipFree(p->Yd);
+    (void)hipFree(p->MY0);
+    (void)hipFree(p->coef);
+    (void)hipFree(p->state);
+    (void)hipFree(p->partials);
+    (void)hipFree(p->s_dev);
+    if (p->s_host) (void)hipHostFree(p->s_host);
     delete p;
 }
 
@@ -211,8 +211,8 @@ static rkl_status select_batch_policy(rkl_plan_s* p, int policy) {
     if (p->batch && policy == p->batch_policy) return RKL_OK;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hipfail(e, "policy sync");
-    if (p->graph_exec) { hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
-    if (p->graph) { hipGraphDestroy(p->graph); p->graph = nullptr; }
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
     batch_free(p->batch);
     p->batch = nullptr;
     p->batch_policy = policy;
@@ -274,10 +274,10 @@ rkl_status rkl_autotune_batched(rkl_plan_t p, const double* T, const void* b, co
         if (e != hipSuccess) { res = hipfail(e, "batched autotune"); break; }
         if (best < 0 || t < best_t) { best = pol; best_t = t; }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    hipStreamSynchronize(s);
-    hipFree(W);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(W);
     p->prof = saved_prof;
     if (res != RKL_OK) {
         select_batch_policy(p, saved);
@@ -318,8 +318,8 @@ static rkl_status select_variant(rkl_plan_s* p, int v) {
         if (!p->Yc) {
             if (hipMalloc(&p->Yc, sizeof(double) * p->total) != hipSuccess ||
                 hipMalloc(&p->Yd, sizeof(double) * p->total) != hipSuccess) {
-                hipGetLastError();
-                hipFree(p->Yc);
+                (void)hipGetLastError();
+                (void)hipFree(p->Yc);
                 p->Yc = nullptr;
                 return fail(RKL_ENOMEM, "stage buffer allocation failed");
             }
@@ -374,7 +374,7 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
               hipMalloc(&p->s_dev, sizeof(int32_t)) == hipSuccess &&
               hipHostMalloc((void**)&p->s_host, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
-        hipGetLastError();
+        (void)hipGetLastError();
         free_plan(p);
         return fail(RKL_ENOMEM, "device allocation failed");
     }
@@ -400,7 +400,7 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
 
 rkl_status rkl_destroy(rkl_plan_t p) {
     if (!p) return RKL_OK;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     free_plan(p);
     return RKL_OK;
 }
@@ -506,7 +506,7 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
             // owned by the plan from here on (prof_clear destroys them)
             HIPCHECK(hipEventCreate(&e0), "event create");
             if (hipEventCreate(&e1) != hipSuccess) {
-                hipEventDestroy(e0);
+                (void)hipEventDestroy(e0);
                 return fail(RKL_EDEVICE, "event create");
             }
             rec = p->prof_recs.size();
@@ -561,7 +561,7 @@ static rkl_status euler_substeps(rkl_plan_t p, int32_t g, double* T, const void*
         if (p->prof) {
             HIPCHECK(hipEventCreate(&e0), "event create");
             if (hipEventCreate(&e1) != hipSuccess) {
-                hipEventDestroy(e0);
+                (void)hipEventDestroy(e0);
                 return fail(RKL_EDEVICE, "event create");
             }
             rec = p->prof_recs.size();
@@ -693,10 +693,10 @@ rkl_status rkl_autotune(rkl_plan_t p, int32_t g, const double* T, const void* b,
             hipEventElapsedTime(&t, e0, e1) != hipSuccess) { res = fail(RKL_EDEVICE, "autotune timing"); break; }
         if (best < 0 || t < best_t) { best = v; best_t = t; }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    hipStreamSynchronize(s);
-    hipFree(W);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(W);
     p->prof = saved_prof;
     if (res != RKL_OK) {
         p->variant = saved;
@@ -774,19 +774,19 @@ rkl_status rkl_graph_capture(rkl_plan_t p, double* T, const void* b, const doubl
     hipStream_t cap;
     HIPCHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) { hipStreamDestroy(cap); return hipfail(e, "begin capture"); }
+    if (e != hipSuccess) { (void)hipStreamDestroy(cap); return hipfail(e, "begin capture"); }
     BatchBuffers bb{T, b, dt_hyp, s_out, p->Ya, p->Yb, p->MY0, p->coef, p->state};
     hipError_t le = batch_launch(p->batch, bb, cap);
     hipGraph_t gr = nullptr;
     e = hipStreamEndCapture(cap, &gr);
-    hipStreamDestroy(cap);
-    if (le != hipSuccess) { if (gr) hipGraphDestroy(gr); return hipfail(le, "batched launch under capture"); }
+    (void)hipStreamDestroy(cap);
+    if (le != hipSuccess) { if (gr) (void)hipGraphDestroy(gr); return hipfail(le, "batched launch under capture"); }
     if (e != hipSuccess) return hipfail(e, "end capture");
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-    if (e != hipSuccess) { hipGraphDestroy(gr); return hipfail(e, "graph instantiate"); }
-    if (p->graph_exec) hipGraphExecDestroy(p->graph_exec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    if (e != hipSuccess) { (void)hipGraphDestroy(gr); return hipfail(e, "graph instantiate"); }
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     p->graph = gr;
     p->graph_exec = ex;
     (void)s;

@@ -242,7 +242,7 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
     bp->kmode = gc[0].kmode;
     if (hipMalloc(&bp->grids, sizeof(BatchGrid) * n) != hipSuccess ||
         hipMalloc(&bp->items_dev, sizeof(int2) * item_list.size()) != hipSuccess) {
-        hipGetLastError();
+        (void)hipGetLastError();
         batch_free(bp);
         why = "device allocation failed";
         return RKL_ENOMEM;
@@ -250,7 +250,7 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
     if (hipMemcpy(bp->grids, h.data(), sizeof(BatchGrid) * n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(bp->items_dev, item_list.data(), sizeof(int2) * item_list.size(), hipMemcpyHostToDevice) !=
             hipSuccess) {
-        hipGetLastError();
+        (void)hipGetLastError();
         batch_free(bp);
         why = "batched plan upload failed";
         return RKL_EDEVICE;
@@ -261,8 +261,8 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
 
 void batch_free(BatchPlan* bp) {
     if (!bp) return;
-    hipFree(bp->grids);
-    hipFree(bp->items_dev);
+    (void)hipFree(bp->grids);
+    (void)hipFree(bp->items_dev);
     delete bp;
 }
 
@@ -306,7 +306,7 @@ hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st,
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (events && j >= 2) {
             if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
-            if ((e = hipEventCreate(&e1)) != hipSuccess) { hipEventDestroy(e0); return e; }
+            if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return e; }
             events->push_back({e0, e1});
             if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
         }
