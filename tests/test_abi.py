@@ -98,3 +98,51 @@ def test_batch_policy_table():
     assert len(seen) == n           # no duplicate policies
     with pytest.raises(rkl.RklError):
         rkl.rkl_batch_policy_info(n)
+
+
+def test_c_program_uses_the_abi(tmp_path):
+    """A plain C program (no Python, no torch) against include/rkl.h and
+    librkl.so: descriptor validation, status codes, the thread's error
+    message and the variant table, all answered before any device call."""
+    import subprocess
+    lib = rkl.load()
+    libdir = os.path.dirname(rkl.LIB_PATH)
+    src = tmp_path / "use_abi.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <string.h>
+#include "rkl.h"
+int main(void) {
+    rkl_grid_desc g;
+    memset(&g, 0, sizeof g);
+    g.ndim = 3; g.n[0] = 8; g.n[1] = 8; g.n[2] = 8;
+    g.h[0] = g.h[1] = g.h[2] = 0.1;
+    g.kappa0 = 1.0; g.rho = 1.0; g.gamma = 2.0; g.cp = 0.5;
+    g.boundary[0] = 7;                       /* not a boundary kind */
+    rkl_plan_t p = (rkl_plan_t)1;
+    rkl_status st = rkl_plan(&g, 1, NULL, &p);
+    if (st != RKL_EINVAL || p != NULL || strstr(rkl_last_error(), "boundary[0]") == NULL) return 1;
+    g.boundary[0] = RKL_BC_PERIODIC;
+    g.saturation = RKL_SAT_UPWIND;           /* phi = 0 with saturation */
+    if (rkl_plan(&g, 1, NULL, &p) != RKL_EINVAL || strstr(rkl_last_error(), "phi") == NULL) return 2;
+    rkl_options o = {RKL_MIXED, -1, 1, RKL_RKL2};   /* smax below 2 */
+    g.saturation = RKL_SAT_NONE;
+    if (rkl_plan(&g, 1, &o, &p) != RKL_EINVAL) return 3;
+    int n = rkl_variant_count(), tx, ty, tz, fuse, fused = 0;
+    for (int v = 0; v < n; ++v) {
+        if (rkl_variant_info(v, &tx, &ty, &tz, &fuse) != RKL_OK) return 4;
+        fused += fuse == 2;
+    }
+    if (rkl_variant_info(n, &tx, &ty, &tz, &fuse) != RKL_EINVAL) return 5;
+    if (rkl_destroy(NULL) != RKL_OK) return 6;
+    printf("%d %d\n", n, fused);
+    return 0;
+}
+''')
+    exe = tmp_path / "use_abi"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                           "-L", libdir, "-lrkl", "-Wl,-rpath," + libdir])
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, (out.returncode, out.stderr)
+    n, fused = (int(x) for x in out.stdout.split())
+    assert n == rkl.rkl_variant_count() and fused >= 1
