@@ -39,8 +39,9 @@ KERNEL_SOURCES = {
     1: ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_kernels.hip"],
     2: ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_fused.h",
         "paper_1702_05487_amd/csrc/rkl_fused.hip"],
+    "batch": ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_batch.hip"],
 }
-KERNEL_NAMES = {1: "stage_kernel", 2: "fused2_kernel"}
+KERNEL_NAMES = {1: "stage_kernel", 2: "fused2_kernel", "batch": "batch_stage_kernel"}
 
 
 def bytes_per_cell_stage(precision, fuse):
@@ -80,8 +81,11 @@ def summarize_counters(fetch_csv, write_csv, workload, precision, fuse):
     WRITE_SIZE; KiB per dispatch).  Each counter is scaled by the factor that
     makes it read 1 GiB for the plain 1 GiB device copy that starts the
     calibration run.  Stage-1 launches (the first stencil launch after each finalize
-    launch) are left out: the measured kernel is stages j >= 2.  Writes the
-    JSON that traffic_for reads and returns it."""
+    launch) are left out: the measured kernel is stages j >= 2.  For the
+    batched workload (fuse "batch") the launches are the stage launches j >= 2
+    of the last, eagerly launched super-step, and the figure is their average
+    per launch, like the roofline's.  Writes the JSON that traffic_for reads
+    and returns it."""
     import csv
 
     def per_dispatch(path, counter):
@@ -100,7 +104,12 @@ def summarize_counters(fetch_csv, write_csv, workload, precision, fuse):
         if not copies:
             raise SystemExit("no copy-calibration dispatch in the counter file")
         vals, after_finalize = [], False
-        for d in sorted(disp):
+        if fuse == "batch":
+            # the last (eager) batched super-step: its stage launches after the
+            # last reduce launch, stage 1 left out
+            last = max(d for d in disp if "batch_reduce" in disp[d][0])
+            vals = [disp[d][1] for d in sorted(disp) if d > last and KERNEL_NAMES[fuse] in disp[d][0]][1:]
+        for d in sorted(disp) if fuse != "batch" else []:
             name, v = disp[d]
             if "finalize_kernel" in name:
                 after_finalize = True
@@ -191,6 +200,7 @@ def bench_batched(args, torch, inputs, rkl):
     s1 = s_out.cpu().numpy().astype(np.int64)
     alg = 48.0 * float((cells * (s1 - 1)).sum())       # stage j >= 2 launches, 48 B per cell-stage
     achieved = alg / (ms / 1e3) / 1e9
+    traffic = traffic_for("patches_2000", "mixed", "batch")   # average bytes per stage j >= 2 launch
     flags = max(plan.query(g)[2] for g in range(0, len(descs), 97))
     sample = None
     if not args.no_cpu_baseline:
@@ -230,7 +240,7 @@ def bench_batched(args, torch, inputs, rkl):
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
             "kernel": "batch_stage_kernel (stages j>=2, eager launches)", "bytes_per_cell_stage": 48.0,
             "avg_launch_ms": ms / launches, "launches": launches,
             "copy_GBs": ceil, "frac_of_copy": achieved / ceil,
@@ -419,8 +429,9 @@ def main():
     ap.add_argument("--fuse", type=int, default=1, help="stages per launch of the kernel summarized")
     args = ap.parse_args()
     if args.counters_summary:
+        fuse = "batch" if args.workload == "patches_2000" else args.fuse
         print(json.dumps(summarize_counters(*args.counters_summary, args.workload,
-                                            WORKLOADS[args.workload][1], args.fuse)))
+                                            WORKLOADS[args.workload][1], fuse)))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus %d" % args.gpus,
@@ -435,18 +446,18 @@ def main():
 
     builder, precision = WORKLOADS[args.workload]
     rkl.load(build_if_missing=True)
-    if args.workload == "patches_2000":
-        print(json.dumps(bench_batched(args, torch, inputs, rkl)), flush=True)
-        return
-    if args.workload == "spitzer_256_subcycle":
-        print(json.dumps(bench_subcycle(args, torch, inputs, rkl)), flush=True)
-        return
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "patches_2000":
+        print(json.dumps(bench_batched(args, torch, inputs, rkl)), flush=True)
+        return
+    if args.workload == "spitzer_256_subcycle":
+        print(json.dumps(bench_subcycle(args, torch, inputs, rkl)), flush=True)
+        return
     dev = torch.device("cuda:0")
     w = getattr(inputs, builder)(device=dev)       # fields generated on the GPU
     plan = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision=precision)
