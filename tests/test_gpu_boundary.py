@@ -2,7 +2,8 @@
 at every stage) on the GPU through the C ABI, against the oracle's outflow
 form.
 
-Bars: FP64 rel-L1 <= 1e-12, mixed <= 1e-5, identical stage counts; every
+Bars: FP64 rel-L1 <= 1e-12, mixed <= 1e-5, identical stage counts (RKL2,
+and RKL1, AAG and sub-cycling in FP64); every
 one-stage variant and the batched launch give the same bits; two-stage
 variants are refused for grids that are not periodic.
 """
@@ -198,4 +199,32 @@ def test_outflow_96_full_grid(torch_cuda):
     got = Td.cpu().numpy()
     print("outflow 96^3: rel-L1 %.3e, change rel-L1 %.3e" % (rel_l1(got, ref), rel_l1(got - T, ref - T)))
     assert s == 16
+    assert rel_l1(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("method", ["rkl1", "aag", "subcycle"])
+def test_outflow_other_integrators(torch_cuda, method):
+    """RKL1, AAG and explicit sub-cycling on a grid with outflow axes, FP64,
+    against the oracle's same integrator"""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    n, h, ndim, p, T, b = make_case("3d_all_open_upwind")
+    g = oracle_grid(n, h, ndim, p)
+    plan = rkl.Plan([lib_desc(n, h, ndim, p)], scheme="rkl1" if method == "rkl1" else "rkl2")
+    Td = to_dev(torch, T, torch.float64)
+    bd = to_dev(torch, b, torch.float64)
+    dt = 9.0 * oracle.dt_par(g, T)
+    if method == "rkl1":
+        c = plan.superstep(Td, bd, dt)
+        ref, c_ref, _ = oracle.superstep_rkl1(g, T, b, dt)
+    elif method == "aag":
+        c = plan.aag(Td, bd, dt, 0.01)
+        ref, c_ref = oracle.aag_superstep(g, T, b, dt, 0.01)
+    else:
+        c = plan.subcycle(Td, bd, dt)
+        ref, c_ref = oracle.subcycle(g, T, b, dt)
+    plan.close()
+    got = Td.cpu().numpy()
+    print("outflow", method, c, "rel-L1 %.3e" % rel_l1(got, ref))
+    assert c == c_ref
     assert rel_l1(got, ref) <= 1e-12
