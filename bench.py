@@ -33,6 +33,8 @@ WORKLOADS = {
     "saturated_512_upwind": ("saturated_512_upwind", "mixed"),
     "fused_768": ("fused_768", "mixed"),
     "patches_2000": ("patch_set", "mixed"),   # batched, graph-captured
+    "patches_2000_fp64": ("patch_set", "fp64"),   # the same, FP64 throughout
+    "patches_2000_fp64_loop": ("patch_set", "fp64"),   # plain FP64: one rkl_superstep per patch
     "spitzer_256_subcycle": ("spitzer_256", "fp64"),   # explicit sub-cycling over the same dt_hyp
 }
 KERNEL_SOURCES = {
@@ -62,10 +64,17 @@ def kernel_hash(fuse):
     return h.hexdigest()[:16]
 
 
+def traffic_path(name, precision, fuse):
+    """profiles/<kernel>_<workload>[_<precision>]_traffic.json (the precision
+    is left out where the workload's name already ends with it)"""
+    tag = name if name.endswith("_" + precision) else "%s_%s" % (name, precision)
+    return os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (KERNEL_NAMES[fuse], tag))
+
+
 def traffic_for(name, precision, fuse):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
     counter runs, if they were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.json" % (KERNEL_NAMES[fuse], name, precision))
+    path = traffic_path(name, precision, fuse)
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -131,8 +140,7 @@ def summarize_counters(fetch_csv, write_csv, workload, precision, fuse):
          "kernel_hash": kernel_hash(fuse), "fetch_factor": ff, "write_factor": wf,
          "read_bytes_per_launch": rd, "write_bytes_per_launch": wr, "bytes_per_launch": rd + wr,
          "dispatches": [nf, nw]}
-    path = os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.json" % (KERNEL_NAMES[fuse], workload, precision))
-    with open(path, "w") as fh:
+    with open(traffic_path(workload, precision, fuse), "w") as fh:
         json.dump(d, fh, indent=1)
         fh.write("\n")
     return d
@@ -155,52 +163,94 @@ def copy_ceiling(torch):
     return gbs
 
 
-def bench_batched(args, torch, inputs, rkl):
+def bench_batched(args, torch, inputs, rkl, precision="mixed", loop=False):
     """2000 independent periodic patches (edges log-uniform in [16, 64], own
     fields, dt_hyp for s_p uniform in [4, 40]), one super-step of all of them
-    per step: the captured HIP graph of rkl_superstep_batched replayed, with
-    the batched tile policy picked by the autotuner first.  The roofline
-    comes from the same launches run eagerly right after the timed replays,
-    each stage launch of j >= 2 timed with HIP events."""
+    per step.  Batched form: the captured HIP graph of rkl_superstep_batched
+    replayed, with the batched tile policy picked by the autotuner first; its
+    roofline comes from the same launches run eagerly right after the timed
+    replays, each stage launch of j >= 2 timed with HIP events.  Loop form
+    (plain, FP64): the host calls rkl_superstep once per patch, with the
+    one-grid stencil variant the autotuner picks on the largest patch; its
+    roofline comes from one more super-step of every patch from the initial
+    fields, after the timed ones, with its stage launches j >= 2 timed."""
     import numpy as np
     ps = inputs.patch_set(2000, device="cuda:0")
     descs = [rkl.grid_desc(n, (1 / 64,) * 3, ndim=3, **ps.params) for n in ps.n]
+    bdtype = torch.float32 if precision == "mixed" else torch.float64
+    bpc = 48.0 if precision == "mixed" else 64.0      # algorithmic bytes per cell-stage, stages j >= 2
     T0 = torch.cat([t.reshape(-1) for t in ps.T]).contiguous()
-    b = torch.cat([x.reshape(-1) for x in ps.b]).to(torch.float32).contiguous()
+    b = torch.cat([x.reshape(-1) for x in ps.b]).to(bdtype).contiguous()
     ps.T = ps.b = None
-    plan = rkl.Plan(descs, precision="mixed", smax=48)
+    plan = rkl.Plan(descs, precision=precision, smax=48)
     off = plan.offsets()
     cells = np.array(ps.cells, dtype=np.int64)
     dts = [ps.ratio[p] * plan.dt_par(T0[off[p]:off[p + 1]], grid=p) for p in range(len(descs))]
     dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
     s_out = torch.zeros(len(descs), dtype=torch.int32, device="cuda:0")
-    s_acc = torch.zeros(len(descs), dtype=torch.int64, device="cuda:0")
-    policy, tuned_ms = plan.autotune_batched(T0, b, dt, reps=2)   # tile policy by timed search
     T = T0.clone()
-    plan.graph_capture(T, b, dt, s_out)
+    stream = rkl.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if loop:
+        big = int(cells.argmax())
+        policy, tuned_ms = rkl.rkl_autotune(plan.handle, big, *plan._tb(big, T0[off[big]:off[big + 1]],
+                                                                        b[3 * off[big]:3 * off[big + 1]]),
+                                            dts[big], 2, stream)
+        ptrs = [(rkl.ctypes.c_void_p(T[off[p]:].data_ptr()), rkl.ctypes.c_void_p(b[3 * off[p]:].data_ptr()))
+                for p in range(len(descs))]
+
+        def step(s_host):
+            for p in range(len(descs)):
+                s_host[p] = rkl.rkl_superstep(plan.handle, p, ptrs[p][0], ptrs[p][1], dts[p], stream)
+    else:
+        policy, tuned_ms = plan.autotune_batched(T0, b, dt, reps=2)   # tile policy by timed search
+        plan.graph_capture(T, b, dt, s_out)
+
+        def step(s_host):
+            plan.graph_launch()
+            s_acc.add_(s_out)
+    s_acc = torch.zeros(len(descs), dtype=torch.int64, device="cuda:0")
+    s_host = np.zeros(len(descs), dtype=np.int64)
+    s_loop = np.zeros(len(descs), dtype=np.int64)
     for _ in range(args.warmup):
-        plan.graph_launch()
+        step(s_host)
     T.copy_(T0)
+    s_acc.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plan.graph_launch()
-        s_acc += s_out
+        step(s_host)
+        s_loop += s_host
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    s_tot = s_acc.cpu().numpy()
+    s_tot = s_loop if loop else s_acc.cpu().numpy()
     cell_stages = float((cells * s_tot).sum())
-    # roofline: eager launches of the same super-step from the initial fields
-    T.copy_(T0)
-    torch.cuda.synchronize()
-    rkl.rkl_profile(plan.handle, 1)
-    plan.superstep_batched(T, b, dt, s_out)
-    ms, launches, _ = rkl.rkl_profile_read(plan.handle, 1)
-    rkl.rkl_profile(plan.handle, 0)
-    s1 = s_out.cpu().numpy().astype(np.int64)
-    alg = 48.0 * float((cells * (s1 - 1)).sum())       # stage j >= 2 launches, 48 B per cell-stage
-    achieved = alg / (ms / 1e3) / 1e9
-    traffic = traffic_for("patches_2000", "mixed", "batch")   # average bytes per stage j >= 2 launch
+    if loop:
+        # roofline: the first super-step of every patch from the initial
+        # fields, run again with its stage launches j >= 2 timed (one event
+        # pair per launch; the host submits each launch while the GPU waits,
+        # so an interval also holds the submission latency)
+        T.copy_(T0)
+        torch.cuda.synchronize()
+        rkl.rkl_profile(plan.handle, 1)
+        step(s_host)
+        ms, launches, profiled_cs = rkl.rkl_profile_read(plan.handle, 1)
+        rkl.rkl_profile(plan.handle, 0)
+        s1 = s_host.copy()
+        achieved = bpc * profiled_cs / (ms / 1e3) / 1e9
+        kernel = "stage_kernel (stages j>=2 of the per-patch super-steps)"
+        traffic = None
+    else:
+        # roofline: eager launches of the same super-step from the initial fields
+        T.copy_(T0)
+        torch.cuda.synchronize()
+        rkl.rkl_profile(plan.handle, 1)
+        plan.superstep_batched(T, b, dt, s_out)
+        ms, launches, _ = rkl.rkl_profile_read(plan.handle, 1)
+        rkl.rkl_profile(plan.handle, 0)
+        s1 = s_out.cpu().numpy().astype(np.int64)
+        achieved = bpc * float((cells * (s1 - 1)).sum()) / (ms / 1e3) / 1e9
+        kernel = "batch_stage_kernel (stages j>=2, eager launches)"
+        traffic = traffic_for(args.workload, precision, "batch")   # average bytes per stage j >= 2 launch
     flags = max(plan.query(g)[2] for g in range(0, len(descs), 97))
     sample = None
     if not args.no_cpu_baseline:
@@ -217,6 +267,12 @@ def bench_batched(args, torch, inputs, rkl):
     del T, T0, b
     torch.cuda.empty_cache()
     ceil = copy_ceiling(torch)
+    if loop:
+        launch = "host loop, one rkl_superstep per patch"
+        tile = {"variant": policy, "tile": list(rkl.rkl_variant_info(policy)[:3])}
+    else:
+        launch = "hipGraph replay, one launch per stage"
+        tile = {"tile_policy": policy, "policy_half_rows_tile_z": list(rkl.rkl_batch_policy_info(policy))}
     out = {
         "metric": "cell-stage updates/s",
         "value": cell_stages / sec,
@@ -228,33 +284,31 @@ def bench_batched(args, torch, inputs, rkl):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 flux + f64 recurrence",
+        "dtype": "f64" if precision == "fp64" else "f32 flux + f64 recurrence",
         "data": "synthetic",
-        "config": {
-            "workload": "patches_2000", "patches": len(descs), "cells": int(cells.sum()),
-            "stages_min": int(s1.min()), "stages_max": int(s1.max()), "precision": "mixed",
+        "config": dict({
+            "workload": args.workload, "patches": len(descs), "cells": int(cells.sum()),
+            "stages_min": int(s1.min()), "stages_max": int(s1.max()), "precision": precision,
             "kappa_par": "T^2.5", "kperp_ratio": ps.params["kperp_ratio"], "limiter": "MC",
-            "saturation": "off", "launch": "hipGraph replay, one launch per stage", "flags": int(flags),
-            "tile_policy": policy, "policy_half_rows_tile_z": list(rkl.rkl_batch_policy_info(policy)),
-            "autotuned_ms_per_step": tuned_ms,
-        },
+            "saturation": "off", "launch": launch, "flags": int(flags),
+        }, autotuned_ms_per_step=tuned_ms, **tile),
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-            "kernel": "batch_stage_kernel (stages j>=2, eager launches)", "bytes_per_cell_stage": 48.0,
+            "kernel": kernel, "bytes_per_cell_stage": bpc,
             "avg_launch_ms": ms / launches, "launches": launches,
             "copy_GBs": ceil, "frac_of_copy": achieved / ceil,
         },
     }
     if sample is not None:
-        out["cpu_baseline"], out["accuracy"] = cpu_baseline_patches(sample, ps.params)
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline_patches(sample, ps.params, precision, launch)
     return out
 
 
-def cpu_baseline_patches(sample, params):
-    """The oracle, untuned, on the first patches of the batched workload (one
-    super-step each, one host core), and the error of the library's batched
-    mixed-precision result for those patches against it."""
+def cpu_baseline_patches(sample, params, precision, launch):
+    """The oracle, untuned, on the first patches of the patch workload (one
+    super-step each, one host core), and the error of the library's result
+    for those patches against it."""
     import numpy as np
     import oracle
     t0 = time.perf_counter()
@@ -278,7 +332,7 @@ def cpu_baseline_patches(sample, params):
             "sample": "one super-step of the first %d patches (%d cell-stages, %.1f s serial)"
                       % (len(sample), cs, sec), "host": host_cpu()}
     acc = {"rel_l1": err / ref_sum, "linf": linf, "rel_l1_change": err / chg_sum, "same_stage_counts": same_s,
-           "sample": "the same patches and super-step, library (mixed, batched) vs oracle (FP64)"}
+           "sample": "the same patches and super-step, library (%s, %s) vs oracle (FP64)" % (precision, launch)}
     return base, acc
 
 
@@ -429,7 +483,7 @@ def main():
     ap.add_argument("--fuse", type=int, default=1, help="stages per launch of the kernel summarized")
     args = ap.parse_args()
     if args.counters_summary:
-        fuse = "batch" if args.workload == "patches_2000" else args.fuse
+        fuse = "batch" if args.workload in ("patches_2000", "patches_2000_fp64") else args.fuse
         print(json.dumps(summarize_counters(*args.counters_summary, args.workload,
                                             WORKLOADS[args.workload][1], fuse)))
         return
@@ -452,8 +506,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.workload == "patches_2000":
-        print(json.dumps(bench_batched(args, torch, inputs, rkl)), flush=True)
+    if builder == "patch_set":
+        print(json.dumps(bench_batched(args, torch, inputs, rkl, precision, args.workload.endswith("_loop"))),
+              flush=True)
         return
     if args.workload == "spitzer_256_subcycle":
         print(json.dumps(bench_subcycle(args, torch, inputs, rkl)), flush=True)

@@ -25,9 +25,20 @@
 namespace rkl {
 
 constexpr int kBT = 256;        // threads per batched workgroup
-constexpr int kPL = 400;        // LDS plane capacity, (bx+2)(by+2)
-constexpr int kFX = 320;        // x-face capacity per buffer, (bx+1) by
-constexpr int kFY = 320;        // y-face capacity per buffer, bx (by+1)
+
+// LDS capacities of the batched tile, per element type: a plane (bx+2)(by+2),
+// x faces (bx+1) by and y faces bx (by+1) per buffer.  In FP64 the plane
+// capacity keeps the tile's 15 planes and 4 face buffers at 51.5 KB, so that
+// three workgroups share the 160 KB of a CU, as many as the FP64 kernel's
+// registers allow; tiles whose rows are too wide for it get fewer rows.
+template <typename R>
+struct Cap {
+    static constexpr int PL = 400, FX = 320, FY = 320;
+};
+template <>
+struct Cap<double> {
+    static constexpr int PL = 344, FX = 320, FY = 320;
+};
 
 struct BatchGrid {
     GridConst gc;
@@ -154,7 +165,7 @@ __device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int
 template <typename R, bool LIM, int SAT, int KM>
 __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int2* __restrict__ items,
                                                           int stage) {
-    __shared__ TileLds<R, kPL, kFX, kFY> L;
+    __shared__ TileLds<R, Cap<R>::PL, Cap<R>::FX, Cap<R>::FY> L;
     const int2 it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const GridState st = P.state[it.x];
     if (st.s < stage || (st.flags & RKL_FLAG_STAGES)) return;   // uniform over the block
@@ -164,7 +175,7 @@ __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int
 // Tile policies of the batched launch: z-chunk length and row width.  Rows
 // are the grid's full width (up to 64 cells), or half of it for grids wider
 // than 32 cells (twice the tiles, shorter halo rows); by fills the 256
-// threads.
+// threads, as far as the plane fits the precision's LDS capacity.
 struct BatchPolicy {
     int half_rows;
     int bz;
@@ -178,11 +189,12 @@ void batch_policy_info(int policy, int* half_rows, int* bz) {
     *bz = kPolicies[policy].bz;
 }
 
-static void choose_tile(const GridConst& g, int policy, int& bx, int& by, int& bz) {
+static void choose_tile(const GridConst& g, int policy, int plcap, int& bx, int& by, int& bz) {
     const BatchPolicy& P = kPolicies[policy];
     bx = std::min(g.n0, 64);
     if (P.half_rows && g.n0 > 32) bx = std::min((g.n0 + 1) / 2, 32);
     by = std::min(std::min(g.n1, kBT / bx), 64);
+    while (by > 1 && (bx + 2) * (by + 2) > plcap) --by;
     bz = std::min(g.n2, P.bz);
 }
 
@@ -194,6 +206,10 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
         why = "batched tile policy out of range";
         return RKL_EINVAL;
     }
+    const bool f32 = precision == RKL_MIXED;
+    const int plcap = f32 ? Cap<float>::PL : Cap<double>::PL;
+    const int fxcap = f32 ? Cap<float>::FX : Cap<double>::FX;
+    const int fycap = f32 ? Cap<float>::FY : Cap<double>::FY;
     const int n = (int)desc.size();
     std::vector<BatchGrid> h(n);
     int64_t items = 0;
@@ -207,8 +223,8 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
         BatchGrid& B = h[g];
         B.gc = gc[g];
         B.off = off[g];
-        choose_tile(gc[g], policy, B.bx, B.by, B.bz);
-        if ((B.bx + 2) * (B.by + 2) > kPL || (B.bx + 1) * B.by > kFX || B.bx * (B.by + 1) > kFY ||
+        choose_tile(gc[g], policy, plcap, B.bx, B.by, B.bz);
+        if ((B.bx + 2) * (B.by + 2) > plcap || (B.bx + 1) * B.by > fxcap || B.bx * (B.by + 1) > fycap ||
             2 * B.bx + 2 * B.by + 4 > kBT) {
             why = "internal: batched tile shape exceeds the LDS layout";
             return RKL_EINVAL;
