@@ -32,6 +32,7 @@ WORKLOADS = {
     "saturated_512_fp64": ("saturated_512", "fp64"),
     "saturated_512_upwind": ("saturated_512_upwind", "mixed"),
     "fused_768": ("fused_768", "mixed"),
+    "fused_768_fp64": ("fused_768", "fp64"),   # the 768^3 workload in FP64 (one-stage kernels only)
     "patches_2000": ("patch_set", "mixed"),   # batched, graph-captured
     "patches_2000_fp64": ("patch_set", "fp64"),   # the same, FP64 throughout
     "patches_2000_fp64_loop": ("patch_set", "fp64"),   # plain FP64: one rkl_superstep per patch
@@ -570,7 +571,7 @@ def main():
         "dtype": "f64" if precision == "fp64" else "f32 flux + f64 recurrence",
         "data": "synthetic",
         "config": {
-            "workload": w.name, "grid": list(w.n), "stages": s_last, "precision": precision,
+            "workload": w.name.replace("_" + w.precision, "_" + precision), "grid": list(w.n), "stages": s_last, "precision": precision,
             "kappa_par": "T^2.5", "kperp_ratio": w.params["kperp_ratio"],
             "limiter": "MC" if w.params["limiter"] else "mean",
             "saturation": ["off", "central", "upwind"][w.params["saturation"]],
