@@ -400,6 +400,8 @@ int orc_superstep_rkl1(const orc_grid *g, double *T, const double *b, double dt_
  *   dt_p s / (2 sqrt(nu)) [(1+sqrt(nu))^{2s} - (1-sqrt(nu))^{2s}]
  *                         / [(1+sqrt(nu))^{2s} + (1-sqrt(nu))^{2s}].
  * orc_aag_gain returns that bracket times s/(2 sqrt(nu)) (the sum over dt_p);
+ * once (1+sqrt(nu))^{2s} is beyond the double range the bracket is 1 to
+ * double precision ((1-sqrt(nu))^{2s} <= 1), and is taken as 1;
  * orc_aag_stages the smallest s whose gain reaches r = dt_hyp/dt_par;
  * orc_aag_superstep scales the sequence of that s to sum to dt_hyp (each
  * sub-step then stays within the sequence built on dt_par) and applies it.
@@ -408,7 +410,8 @@ double orc_aag_gain(int s, double nu)
 {
     const double q = sqrt(nu);
     const double a = pow(1.0 + q, 2.0 * s), c = pow(1.0 - q, 2.0 * s);
-    return s / (2.0 * q) * (a - c) / (a + c);
+    if (isinf(a)) return s / (2.0 * q);
+    return s / (2.0 * q) * ((a - c) / (a + c));   /* the bracket first: s/(2q) a may overflow */
 }
 
 int orc_aag_stages(double r, double nu, int smax)

@@ -110,3 +110,20 @@ def test_aag_conserves_energy():
     Y, s = oracle.aag_superstep(g, T, b, 25.0 * oracle.dt_par(g, T), 0.01)
     assert s == oracle.aag_stages(25.0, 0.01)
     assert abs(Y.sum() - T.sum()) <= 1e-13 * T.sum() * s
+
+
+def test_gain_beyond_the_double_range_of_the_power():
+    # (1 + sqrt(nu))^(2s) of Eq. AAG-STS exceeds the double range once
+    # 2 s ln(1 + sqrt(nu)) > ln(DBL_MAX); the gain, the sum of the sub-step
+    # sequence over dt_p, must still be found there, and the stage search
+    # must still end: for s far beyond, the gain is s / (2 sqrt(nu))
+    nu = 0.1
+    q = np.sqrt(nu)
+    s_over = int(np.log(np.finfo(np.float64).max) / (2 * np.log1p(q))) + 1
+    for s in (s_over - 2, s_over - 1, s_over, s_over + 1, 2 * s_over):
+        g = oracle.aag_gain(s, nu)
+        assert np.isfinite(g)
+        np.testing.assert_allclose(oracle.aag_taus(s, nu, 1.0).sum(), g, rtol=1e-12)
+        assert g > oracle.aag_gain(s - 1, nu)
+    r = 3000.0
+    assert oracle.aag_stages(r, nu, smax=4096) == int(np.ceil(2 * q * r))
