@@ -110,8 +110,10 @@ typedef struct {
  * variant --, the tau*M(Y0) buffer, reduction space and the RKL2 coefficient
  * table for s = 2..smax, Appendix A).  Grids are packed back to back for the
  * batched entry points; rkl_grid_offset gives each grid's first cell.  The
- * device current at this call is the plan's device.  opt may be NULL
- * (RKL_FP64, default variant, default smax).
+ * device current at this call is the plan's device: every later call on the
+ * plan (except rkl_destroy, which switches to it) returns RKL_EINVAL while
+ * another device is current.  opt may be NULL (RKL_FP64, default variant,
+ * default smax).
  * Errors: RKL_EINVAL for a bad descriptor or option (including a two-stage
  * variant for a plan that cannot use it), RKL_ENOMEM, RKL_EDEVICE.
  */
@@ -119,7 +121,7 @@ rkl_status rkl_plan(const rkl_grid_desc *grids, int32_t ngrids, const rkl_option
                     rkl_plan_t *plan_out);
 
 /* rkl_destroy: free the plan and its graph (NULL is accepted).  Synchronises
- * the device. */
+ * the plan's device; the caller's current device is kept. */
 rkl_status rkl_destroy(rkl_plan_t plan);
 
 /* Cells in the packed layout before grid `grid` (b of that grid starts at
@@ -130,7 +132,8 @@ int64_t rkl_grid_offset(rkl_plan_t plan, int32_t grid);
  * rkl_flux_div: out[i] = (gamma-1)/rho * ( -div F_c(T) )_i for one grid
  * (Sec. 3: the face-difference divergence of the flux of Eqs. Fc-Fsat), in
  * the plan's flux precision, written as double.  T, b, out: device pointers
- * of that grid's size; out must not alias T.  No host synchronisation.
+ * of that grid's size; out must not alias T or b (RKL_EINVAL).  No host
+ * synchronisation.
  */
 rkl_status rkl_flux_div(rkl_plan_t plan, int32_t grid, const double *T, const void *b,
                         double *out, void *stream);
@@ -153,7 +156,8 @@ rkl_status rkl_dt_par(rkl_plan_t plan, int32_t grid, const double *T, double *dt
  * dt_hyp/dt_par = (s^2+s-2)/4) is computed on the device (Eq. RKL-s); this
  * entry point reads it back once (one synchronisation of `stream`) to size
  * the launch sequence, and stores it in *s_out (host pointer, may be NULL).
- * RKL_ESTAGES (T unchanged) if s > smax.  b must not alias T.
+ * RKL_ESTAGES (T unchanged) if s > smax.  b must not alias T (RKL_EINVAL;
+ * likewise for the other entry points that take T and b).
  * With scheme RKL_RKL1 the super-step is the first-order scheme: stability
  * polynomial P_s(1 + w1 tau lambda), w1 = 2/(s^2+s), stages Y_1 = Y_0 +
  * w1 tau M(Y_0), Y_j = (2j-1)/j (Y_{j-1} + w1 tau M(Y_{j-1})) - (j-1)/j Y_{j-2},

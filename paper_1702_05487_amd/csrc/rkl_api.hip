@@ -205,6 +205,19 @@ static rkl_status ensure_batch(rkl_plan_s* p) {
     return st == RKL_OK ? RKL_OK : fail(st, why);
 }
 
+// A plan's buffers live on the device that was current at rkl_plan; its
+// launches must go to that device.
+static rkl_status check_plan(const rkl_plan_s* p) {
+    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    int d = -1;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) return hipfail(e, "hipGetDevice");
+    if (d != p->device)
+        return fail(RKL_EINVAL, "the plan belongs to device " + std::to_string(p->device) + ", device " +
+                                    std::to_string(d) + " is current");
+    return RKL_OK;
+}
+
 // Replace the batched launch data by that of `policy`; a captured graph
 // refers to the old data, so it is dropped.
 static rkl_status select_batch_policy(rkl_plan_s* p, int policy) {
@@ -235,15 +248,16 @@ rkl_status rkl_batch_policy_info(int32_t policy, int32_t* half_rows, int32_t* ti
 }
 
 rkl_status rkl_set_batch_policy(rkl_plan_t p, int32_t policy) {
-    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (rkl_status st = check_plan(p)) return st;
     if (policy < 0 || policy >= batch_policy_count()) return fail(RKL_EINVAL, "policy out of range");
     return select_batch_policy(p, policy);
 }
 
 rkl_status rkl_autotune_batched(rkl_plan_t p, const double* T, const void* b, const double* dt_hyp,
                                 int32_t reps, int32_t* best_policy, double* best_ms, void* stream) {
-    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (rkl_status st = check_plan(p)) return st;
     if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
+    if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     if (reps < 1 || reps > 1000) return fail(RKL_EINVAL, "reps must be in [1, 1000]");
     hipStream_t s = (hipStream_t)stream;
     const size_t bytes = sizeof(double) * (size_t)p->total;
@@ -400,8 +414,12 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
 
 rkl_status rkl_destroy(rkl_plan_t p) {
     if (!p) return RKL_OK;
+    // free on the plan's device, then restore the caller's
+    int cur = -1;
+    const bool other = hipGetDevice(&cur) == hipSuccess && cur != p->device && hipSetDevice(p->device) == hipSuccess;
     (void)hipDeviceSynchronize();
     free_plan(p);
+    if (other) (void)hipSetDevice(cur);
     return RKL_OK;
 }
 
@@ -411,13 +429,13 @@ int64_t rkl_grid_offset(rkl_plan_t p, int32_t g) {
 }
 
 rkl_status rkl_set_variant(rkl_plan_t p, int32_t v) {
-    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (rkl_status st = check_plan(p)) return st;
     if (v < 0 || v >= variant_count()) return fail(RKL_EINVAL, "variant out of range");
     return select_variant(p, v);
 }
 
 static rkl_status check_grid(rkl_plan_t p, int32_t g) {
-    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (rkl_status st = check_plan(p)) return st;
     if (g < 0 || g >= p->ngrids) return fail(RKL_EINVAL, "grid index out of range");
     return RKL_OK;
 }
@@ -437,7 +455,7 @@ rkl_status rkl_flux_div(rkl_plan_t p, int32_t g, const double* T, const void* b,
     rkl_status st = check_grid(p, g);
     if (st != RKL_OK) return st;
     if (!T || !b || !out) return fail(RKL_EINVAL, "NULL field pointer");
-    if (out == T) return fail(RKL_EINVAL, "out must not alias T");
+    if (out == T || (const void*)out == b) return fail(RKL_EINVAL, "out must not alias T or b");
     hipStream_t s = (hipStream_t)stream;
     st = reduce_and_finalize(p, g, T, 0.0, 1, nullptr, s);
     if (st != RKL_OK) return st;
@@ -466,6 +484,7 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
     rkl_status st = check_grid(p, g);
     if (st != RKL_OK) return st;
     if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
     hipStream_t s = (hipStream_t)stream;
     st = reduce_and_finalize(p, g, T, dt_hyp, 0, p->s_dev, s);
@@ -597,6 +616,7 @@ rkl_status rkl_subcycle(rkl_plan_t p, int32_t g, double* T, const void* b, doubl
     if (st != RKL_OK) return st;
     if (nsub_out) *nsub_out = 0;
     if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
     if (max_sub < 1) return fail(RKL_EINVAL, "max_sub must be >= 1");
     hipStream_t s = (hipStream_t)stream;
@@ -616,10 +636,13 @@ rkl_status rkl_subcycle(rkl_plan_t p, int32_t g, double* T, const void* b, doubl
     return RKL_OK;
 }
 
-// AAG gain (the sum of the sub-steps over dt_par) of s stages, Eq. AAG-STS
+// AAG gain (the sum of the sub-steps over dt_par) of s stages, Eq. AAG-STS.
+// Where (1+sqrt(nu))^{2s} is beyond the double range, the bracket
+// (a-c)/(a+c) is 1 to double precision (c <= 1).
 static double aag_gain(int s, double nu) {
     const double q = std::sqrt(nu);
     const double a = std::pow(1.0 + q, 2.0 * s), c = std::pow(1.0 - q, 2.0 * s);
+    if (std::isinf(a)) return s / (2.0 * q);
     return s / (2.0 * q) * ((a - c) / (a + c));
 }
 
@@ -629,6 +652,7 @@ rkl_status rkl_aag(rkl_plan_t p, int32_t g, double* T, const void* b, double dt_
     if (st != RKL_OK) return st;
     if (s_out) *s_out = 0;
     if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
     if (!(nu > 0.0 && nu < 1.0)) return fail(RKL_EINVAL, "nu must be in (0, 1)");
     if (max_s < 1) return fail(RKL_EINVAL, "max_s must be >= 1");
@@ -661,6 +685,7 @@ rkl_status rkl_autotune(rkl_plan_t p, int32_t g, const double* T, const void* b,
     rkl_status st = check_grid(p, g);
     if (st != RKL_OK) return st;
     if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     if (reps < 1 || reps > 1000) return fail(RKL_EINVAL, "reps must be in [1, 1000]");
     hipStream_t s = (hipStream_t)stream;
     const size_t bytes = sizeof(double) * (size_t)(p->off[g + 1] - p->off[g]);
@@ -709,7 +734,7 @@ rkl_status rkl_autotune(rkl_plan_t p, int32_t g, const double* T, const void* b,
 }
 
 rkl_status rkl_profile(rkl_plan_t p, int32_t enable) {
-    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (rkl_status st = check_plan(p)) return st;
     HIPCHECK(hipDeviceSynchronize(), "profile sync");
     prof_clear(p);
     p->prof = enable != 0;
@@ -717,7 +742,7 @@ rkl_status rkl_profile(rkl_plan_t p, int32_t enable) {
 }
 
 rkl_status rkl_profile_read(rkl_plan_t p, int32_t fuse, double* ms, int64_t* launches, int64_t* cells) {
-    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (rkl_status st = check_plan(p)) return st;
     if (fuse < 1 || fuse > 3) return fail(RKL_EINVAL, "fuse must be 1, 2 or 3");
     double tot = 0.0;
     int64_t nl = 0, nc = 0;
@@ -750,8 +775,9 @@ rkl_status rkl_query(rkl_plan_t p, int32_t g, int32_t* last_s, double* last_dt_p
 
 rkl_status rkl_superstep_batched(rkl_plan_t p, double* T, const void* b, const double* dt_hyp, int32_t* s_out,
                                  void* stream) {
-    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (rkl_status st = check_plan(p)) return st;
     if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
+    if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     rkl_status st = ensure_batch(p);
     if (st != RKL_OK) return st;
     BatchBuffers bb{T, b, dt_hyp, s_out, p->Ya, p->Yb, p->MY0, p->coef, p->state};
@@ -766,8 +792,9 @@ rkl_status rkl_superstep_batched(rkl_plan_t p, double* T, const void* b, const d
 
 rkl_status rkl_graph_capture(rkl_plan_t p, double* T, const void* b, const double* dt_hyp, int32_t* s_out,
                              void* stream) {
-    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (rkl_status st = check_plan(p)) return st;
     if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
+    if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     rkl_status st = ensure_batch(p);
     if (st != RKL_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -794,7 +821,7 @@ rkl_status rkl_graph_capture(rkl_plan_t p, double* T, const void* b, const doubl
 }
 
 rkl_status rkl_graph_launch(rkl_plan_t p, void* stream) {
-    if (!p) return fail(RKL_EINVAL, "plan is NULL");
+    if (rkl_status st = check_plan(p)) return st;
     if (!p->graph_exec) return fail(RKL_ESTATE, "no graph captured");
     HIPCHECK(hipGraphLaunch(p->graph_exec, (hipStream_t)stream), "graph launch");
     return RKL_OK;

@@ -88,3 +88,25 @@ def test_aag_errors(torch_cuda):
     assert np.array_equal(Td.cpu().numpy(), T)
     assert plan.aag(Td, bd, 0.0, 0.01) == 0
     plan.close()
+
+
+def test_aag_beyond_the_double_range_of_the_gain_power(torch_cuda):
+    """nu = 0.1 and dt_hyp = 3000 dt_par: S = 1898 sub-steps, past the stage
+    count where (1 + sqrt(nu))^(2S) of Eq. AAG-STS exceeds the double range
+    (S > 1291); the library still finds S, the oracle's, and matches the
+    oracle's result"""
+    torch = torch_cuda
+    n, h, ndim, p, T, b = make_case("tiny3d")
+    plan = run_plan(torch, n, h, ndim, p, "fp64")
+    Td = to_dev(torch, T, torch.float64)
+    bd = to_dev(torch, b, torch.float64)
+    g = oracle_grid(n, h, ndim, p)
+    dt = 3000.0 * oracle.dt_par(g, T)
+    c = plan.aag(Td, bd, dt, 0.1, 4096)
+    plan.close()
+    ref, c_ref = oracle.aag_superstep(g, T, b, dt, 0.1, 4096)
+    got = Td.cpu().numpy()
+    print("AAG nu 0.1, 3000 dt_par: S", c, "rel-L1 %.3e" % rel_l1(got, ref), flush=True)
+    assert c == c_ref == int(np.ceil(2 * np.sqrt(0.1) * 3000.0))
+    assert np.isfinite(got).all()
+    assert rel_l1(got, ref) <= 1e-12

@@ -219,6 +219,19 @@ def test_flags_and_errors(torch_cuda):
         plan.superstep(Td.float(), bd, 1e-6)
     with pytest.raises(rkl.RklError):
         plan.superstep(Td, bd, float("nan"))
+    # aliased fields are refused before any launch
+    stream = rkl.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    tp, bp = rkl.ctypes.c_void_p(Td.data_ptr()), rkl.ctypes.c_void_p(bd.data_ptr())
+    before = Td.cpu().numpy()
+    for call in (lambda: rkl.rkl_superstep(plan.handle, 0, tp, tp, 1e-6, stream),
+                 lambda: rkl.rkl_subcycle(plan.handle, 0, tp, tp, 1e-6, 100, stream),
+                 lambda: rkl.rkl_aag(plan.handle, 0, tp, tp, 1e-6, 0.01, 100, stream),
+                 lambda: rkl.rkl_flux_div(plan.handle, 0, tp, bp, bp, stream),
+                 lambda: rkl.rkl_flux_div(plan.handle, 0, tp, bp, tp, stream)):
+        with pytest.raises(rkl.RklError) as e:
+            call()
+        assert e.value.status == rkl.RKL_EINVAL
+    assert np.array_equal(Td.cpu().numpy(), before)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
