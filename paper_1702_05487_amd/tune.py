@@ -38,9 +38,25 @@ def _load(path):
 def _save(path, d):
     os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
     fd, tmp = tempfile.mkstemp(dir=os.path.dirname(path) or ".", prefix=".tune")
-    with os.fdopen(fd, "w") as f:
-        json.dump(d, f, indent=1, sort_keys=True)
-    os.replace(tmp, path)
+    try:
+        with os.fdopen(fd, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except BaseException:
+        try:
+            os.unlink(tmp)
+        except OSError:
+            pass
+        raise
+
+
+def _cached_variant(d, k):
+    """the cached variant index under key k, or None if absent or malformed"""
+    e = d.get(k)
+    v = e.get("variant") if isinstance(e, dict) else None
+    if isinstance(v, int) and not isinstance(v, bool) and 0 <= v < rkl.rkl_variant_count():
+        return v
+    return None
 
 
 def key(plan, grid):
@@ -48,7 +64,7 @@ def key(plan, grid):
     d = plan.descs[grid]
     kind = "const" if d.kappa_exp == 0.0 else ("spitzer" if d.kappa_exp == 2.5 else "power")
     return "|".join(str(x) for x in (
-        torch.cuda.get_device_name(0), tuple(d.n), d.ndim,
+        torch.cuda.get_device_name(torch.cuda.current_device()), tuple(d.n), d.ndim,
         "mixed" if plan.precision == rkl.RKL_MIXED else "fp64",
         "mc" if d.limiter else "mean", ("nosat", "sat", "upwind")[d.saturation], kind,
         "bc%d%d%d" % tuple(d.boundary), rkl.rkl_variant_count()))
@@ -60,9 +76,10 @@ def autotune(plan, T, b, dt_hyp, reps=2, grid=0, cache=None):
     path = cache_path(cache)
     k = key(plan, grid)
     d = _load(path)
-    if k in d and 0 <= d[k].get("variant", -1) < rkl.rkl_variant_count():
-        plan.set_variant(d[k]["variant"])
-        return d[k]["variant"], d[k].get("ms"), True
+    v = _cached_variant(d, k)
+    if v is not None:
+        plan.set_variant(v)
+        return v, d[k].get("ms"), True
     tp, bp = plan._tb(grid, T, b)
     v, ms = rkl.rkl_autotune(plan.handle, grid, tp, bp, dt_hyp, reps,
                              rkl.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))

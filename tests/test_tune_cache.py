@@ -30,3 +30,22 @@ def test_corrupt_or_missing_cache_is_ignored(tmp_path):
     lst.write_text(json.dumps([1, 2]))
     assert tune._load(str(lst)) == {}
     assert tune._load(str(tmp_path / "missing.json")) == {}
+
+
+def test_malformed_entries_are_ignored():
+    from paper_1702_05487_amd import rkl
+    n = rkl.rkl_variant_count()
+    d = {"num": 3, "none": {"ms": 1.0}, "str": {"variant": "2"}, "bool": {"variant": True},
+         "neg": {"variant": -1}, "big": {"variant": n}, "ok": {"variant": n - 1}}
+    for k in ("num", "none", "str", "bool", "neg", "big", "missing"):
+        assert tune._cached_variant(d, k) is None, k
+    assert tune._cached_variant(d, "ok") == n - 1
+
+
+def test_failed_write_leaves_no_temp_file(tmp_path):
+    path = str(tmp_path / "tune.json")
+    try:
+        tune._save(path, {"k": object()})        # not JSON-serialisable
+    except TypeError:
+        pass
+    assert os.listdir(tmp_path) == []
