@@ -265,6 +265,9 @@ def _dev_ptr(t, dtype, numel, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError("%s is on %s; the current device (the plan's) is cuda:%d"
+                         % (name, t.device, torch.cuda.current_device()))
     if t.dtype != dtype:
         raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
     if not t.is_contiguous():
