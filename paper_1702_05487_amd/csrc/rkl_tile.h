@@ -76,6 +76,13 @@ template <typename R>
 __device__ __forceinline__ R mc2(R a, R b) {
     return med3(R(4) * med3(a, b, R(0)), a + b, R(0));
 }
+// FP64 has no median instruction: where m = minmod(a, b) is not zero, a + b
+// has its sign, so the outer median is that sign times min(4|m|, |a+b|);
+// where m is zero, so is that product.  Same values, one emulated median.
+__device__ __forceinline__ double mc2(double a, double b) {
+    const double m = med3(a, b, 0.0);
+    return copysign(fmin(4.0 * fabs(m), fabs(a + b)), m);
+}
 
 // Cell slope along one axis from the one-sided differences (t0-tm)/h and
 // (tp-t0)/h: MC-limited, or their mean (so that the mean of two cell slopes
