@@ -160,26 +160,40 @@ def test_batched_stage_limit_is_flagged(torch_cuda):
     assert not torch.equal(T[off[1]:off[2]], T0[off[1]:off[2]])
 
 
-def test_patches_2000_full_size_sampled(torch_cuda):
+@pytest.mark.parametrize("precision,tol", [("mixed", 1e-5), ("fp64", 1e-12)])
+def test_patches_2000_full_size_sampled(torch_cuda, precision, tol):
     """The 2000-patch workload at full size in the launch configuration that
-    bench.py times (mixed, smax 48, captured graph replayed): whole patches
-    sampled and compared with the oracle -- the six smallest, two drawn at
-    random and the small patch with the most stages."""
+    bench.py times (smax 48, captured graph replayed) with every tile policy
+    (the autotuner picks among them; all give the same bits over the whole
+    packed field): whole patches sampled and compared with the oracle -- the
+    six smallest, two drawn at random and the small patch with the most
+    stages."""
     torch = torch_cuda
     from paper_1702_05487_amd import rkl
     ps = inputs.patch_set(2000, device="cuda:0")
     descs = [lib_desc(n, (1 / 64,) * 3, 3, ps.params) for n in ps.n]
     T0 = torch.cat([t.reshape(-1) for t in ps.T]).contiguous()
-    b = torch.cat([x.reshape(-1) for x in ps.b]).to(torch.float32).contiguous()
-    plan = rkl.Plan(descs, precision="mixed", smax=48)
+    b = torch.cat([x.reshape(-1) for x in ps.b]).to(torch.float32 if precision == "mixed" else torch.float64)
+    b = b.contiguous()
+    ps.T = ps.b = None
+    plan = rkl.Plan(descs, precision=precision, smax=48)
     off = plan.offsets()
     dts = [ps.ratio[p] * plan.dt_par(T0[off[p]:off[p + 1]], grid=p) for p in range(len(descs))]
     dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
     s_out = torch.zeros(len(descs), dtype=torch.int32, device="cuda:0")
-    T = T0.clone()
-    plan.graph_capture(T, b, dt, s_out)
-    plan.graph_launch()
-    s = s_out.cpu().numpy()
+    T = None
+    for pol in range(rkl.rkl_batch_policy_count()):
+        plan.set_batch_policy(pol)
+        Tp = T0.clone()
+        plan.graph_capture(Tp, b, dt, s_out)
+        plan.graph_launch()
+        torch.cuda.synchronize()
+        if T is None:
+            T, s = Tp, s_out.cpu().numpy()
+        else:
+            assert torch.equal(Tp, T), pol
+            assert np.array_equal(s_out.cpu().numpy(), s), pol
+            del Tp
     assert s.min() >= 4 and s.max() <= 40
     cells = np.array(ps.cells)
     order = np.argsort(cells)
@@ -197,7 +211,7 @@ def test_patches_2000_full_size_sampled(torch_cuda):
         To, s_ref, _ = oracle.superstep(g, Tp, bp, dts[p])
         assert s_ref == s[p], p
         err = rel_l1(got[off[p]:off[p + 1]].reshape(shape), To)
-        assert err <= 1e-5, (p, err)
+        assert err <= tol, (p, err)
     plan.close()
 
 
