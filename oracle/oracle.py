@@ -95,9 +95,12 @@ def build(force: bool = False) -> str:
 
 
 def load():
+    """Load the oracle library: the one built from rkl_oracle.c, or the one
+    named by $RKL_ORACLE_LIB (the mutation tests use this to run the pins
+    against deliberately broken copies of the oracle)."""
     global _lib
     if _lib is None:
-        lib = ctypes.CDLL(build())
+        lib = ctypes.CDLL(os.environ.get("RKL_ORACLE_LIB") or build())
         dp = ctypes.POINTER(ctypes.c_double)
         gp = ctypes.POINTER(_CGrid)
         lib.orc_mc.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -110,6 +113,8 @@ def load():
         lib.orc_dt_par.restype = ctypes.c_double
         lib.orc_flux_div.argtypes = [gp, dp, dp, dp]
         lib.orc_flux_div.restype = None
+        lib.orc_face_flux.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.orc_face_flux.restype = ctypes.c_double
         lib.orc_rkl2_fixed.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_double]
         lib.orc_rkl2_fixed.restype = None
         lib.orc_superstep.argtypes = [gp, dp, dp, ctypes.c_double, dp]
@@ -183,6 +188,15 @@ def flux_div(g: Grid, T, b) -> np.ndarray:
     cg = g.c()
     load().orc_flux_div(ctypes.byref(cg), _ptr(T), _ptr(b), _ptr(out))
     return out
+
+
+def face_flux(g: Grid, T, b, cell, d: int) -> float:
+    """Component d of the flux through the +e_d face of cell (i, j, k)."""
+    T = _field(g, T, "T")
+    b = _bfield(g, b)
+    cg = g.c()
+    i, j, k = (int(v) for v in cell)
+    return load().orc_face_flux(ctypes.byref(cg), _ptr(T), _ptr(b), i, j, k, int(d))
 
 
 def rkl2_fixed(g: Grid, T, b, s: int, tau: float) -> np.ndarray:

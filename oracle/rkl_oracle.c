@@ -185,6 +185,14 @@ static double face_flux(const orc_grid *g, const double *T, const double *b,
     return q / (q + Fm) * F[d];
 }
 
+/* Component d of the flux through the +e_d face of cell (i, j, k), as used
+ * by the divergence below (exported for the pins of the face algebra). */
+double orc_face_flux(const orc_grid *g, const double *T, const double *b, int i, int j, int k, int d)
+{
+    const int c[3] = {i, j, k};
+    return face_flux(g, T, b, c, d);
+}
+
 /*
  * out = (gamma-1)/rho * ( -div F_c(T) ), the conservative second-order
  * difference of the face fluxes (Sec. 3).  With rho*eps = rho T/(gamma-1)

@@ -237,3 +237,52 @@ def test_reversing_field_only_conducts_across(r):
     out = oracle.flux_div(g, T[None, None], b).ravel()
     lap = r * kap * (np.roll(T, -1) - 2 * T + np.roll(T, 1)) / h ** 2
     assert np.abs(out - lap).max() <= 1e-12 * max(1.0, np.abs(lap).max())
+
+
+def test_limited_face_gradient_sees_each_cell_through_its_own_slope():
+    """Appendix B (limited transverse gradient): at a face it is the MC of
+    the two cells' own MC-limited slopes, so a cell's pair of one-sided
+    differences enters only through MC of that pair.  Pairs (1, 3), (2, 2)
+    and (3, 1) all have MC = 2 and must give the same face flux, on either
+    side of the face; a pair with another MC (1, 1) must not.  Pairing the
+    four differences across the face instead (L's lower with R's lower) gives
+    1.125 for (1, 3) and 1.375 for (2, 2) beside R's (1.5, 0.5)."""
+    g = oracle.Grid(n=(4, 4, 1), h=(1.0, 1.0, 1.0), ndim=2, limiter=1, kappa0=1.0, kperp_ratio=0.0)
+    b = np.zeros((3, 1, 4, 4))
+    b[0], b[1] = np.cos(np.pi / 6), np.sin(np.pi / 6)
+
+    def flux(left, right):
+        T = np.full((1, 4, 4), 5.0)
+        T[0, 0, 1], T[0, 1, 1], T[0, 2, 1] = 5.0 - left[0], 5.0, 5.0 + left[1]      # cell L = (1, 1)
+        T[0, 0, 2], T[0, 1, 2], T[0, 2, 2] = 6.0 - right[0], 6.0, 6.0 + right[1]    # cell R = (2, 1)
+        return oracle.face_flux(g, T, b, (1, 1, 0), 0)
+
+    r = (1.5, 0.5)
+    same = [flux(p, r) for p in ((1.0, 3.0), (2.0, 2.0), (3.0, 1.0))]
+    assert same[0] == same[1] == same[2]
+    assert flux((1.0, 1.0), r) != same[0]
+    same = [flux((1.5, 0.5), p) for p in ((1.0, 3.0), (2.0, 2.0), (3.0, 1.0))]
+    assert same[0] == same[1] == same[2]
+    assert flux((1.5, 0.5), (1.0, 1.0)) != same[0]
+    # the value itself: G_y = MC(2, MC(1.5, 0.5)) = MC(2, 1) = 1.5 with
+    # MC(a, b) = minmod(2a, 2b, (a+b)/2); G_x = 1; F_x = -kappa b_x (b . G)
+    bx, by = np.cos(np.pi / 6), np.sin(np.pi / 6)
+    assert abs(flux((2.0, 2.0), r) - (-(bx * (bx * 1.0 + by * 1.5)))) < 1e-14
+
+
+def test_face_direction_is_the_normalised_sum():
+    """The face field direction is (b_L + b_R)/|b_L + b_R|: a face between a
+    cell with b = x and one with b = y carries the same flux as the same
+    face in a uniform field along their bisector (an unnormalised mean of
+    the two would give a direction of length 1/sqrt(2))."""
+    g = oracle.Grid(n=(4, 4, 1), h=(0.5, 0.25, 1.0), ndim=2, kappa0=1.0, kperp_ratio=0.1)
+    T = np.linspace(1.0, 2.0, 16).reshape(1, 4, 4) ** 2
+    mixed = np.zeros((3, 1, 4, 4))
+    mixed[0, 0, :, :2] = 1.0          # columns 0, 1: b = x
+    mixed[1, 0, :, 2:] = 1.0          # columns 2, 3: b = y
+    bis = np.zeros((3, 1, 4, 4))
+    bis[0] = bis[1] = np.sqrt(0.5)
+    f_mixed = oracle.face_flux(g, T, mixed, (1, 1, 0), 0)   # +x face of cell (1, 1): an x cell and a y cell
+    f_bis = oracle.face_flux(g, T, bis, (1, 1, 0), 0)
+    assert abs(f_bis) > 0.1
+    assert abs(f_mixed - f_bis) <= 1e-14 * abs(f_bis)
