@@ -39,25 +39,23 @@ namespace rkl {
 
 // ---------------------------------------------------------------- math ----
 // FP32: the hardware square root / reciprocal / reciprocal square root.
-// FP64: the hardware estimate refined by two Newton steps (relative error
-// of the estimate ~2^-23, after two steps at the rounding level).
+// FP64: the hardware estimate y (relative error ~2^-23) corrected once to
+// third order: with e = 1 - x y^2, 1/sqrt(x) = y (1 + e/2 + 3e^2/8 + O(e^3));
+// with e = 1 - x y, 1/x = y (1 + e + e^2 + O(e^3)); the dropped terms are
+// ~2^-66, below the rounding level.
 __device__ __forceinline__ float r_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double r_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float r_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double r_rsqrt(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-x * y, y, 1.0);
-    return fma(0.5 * y, e, y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 __device__ __forceinline__ float r_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double r_rcp(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, y, 1.0);
+    return fma(y, fma(e, e, e), y);
 }
 __device__ __forceinline__ float r_pow(float x, float y) { return powf(x, y); }
 __device__ __forceinline__ double r_pow(double x, double y) { return pow(x, y); }
