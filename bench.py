@@ -65,27 +65,30 @@ def kernel_hash(fuse):
     return h.hexdigest()[:16]
 
 
-def traffic_path(name, precision, fuse):
-    """profiles/<kernel>_<workload>[_<precision>]_traffic.json (the precision
-    is left out where the workload's name already ends with it)"""
+def traffic_path(name, precision, fuse, variant):
+    """profiles/<kernel>_<workload>[_<precision>]_<v|p><n>_traffic.json: the
+    counters of one stencil variant (v) or batched tile policy (p); the
+    precision is left out where the workload's name already ends with it"""
     tag = name if name.endswith("_" + precision) else "%s_%s" % (name, precision)
-    return os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (KERNEL_NAMES[fuse], tag))
+    kind = "p" if fuse == "batch" else "v"
+    return os.path.join(ROOT, "profiles", "%s_%s_%s%d_traffic.json" % (KERNEL_NAMES[fuse], tag, kind, variant))
 
 
-def traffic_for(name, precision, fuse):
+def traffic_for(name, precision, fuse, variant):
     """HBM bytes per launch of the dominant kernel from committed rocprofv3
-    counter runs, if they were taken on the current kernel source."""
-    path = traffic_path(name, precision, fuse)
+    counter runs, if they were taken on the current kernel source with the
+    same variant (or batched tile policy)."""
+    path = traffic_path(name, precision, fuse, variant)
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_hash") != kernel_hash(fuse):
+    if d.get("kernel_hash") != kernel_hash(fuse) or d.get("variant") != variant:
         return None
     return d.get("bytes_per_launch")
 
 
-def summarize_counters(fetch_csv, write_csv, workload, precision, fuse):
+def summarize_counters(fetch_csv, write_csv, workload, precision, fuse, variant):
     """HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc
     runs of this script with --copy-calibration (FETCH_SIZE, then
     WRITE_SIZE; KiB per dispatch).  Each counter is scaled by the factor that
@@ -94,8 +97,9 @@ def summarize_counters(fetch_csv, write_csv, workload, precision, fuse):
     launch) are left out: the measured kernel is stages j >= 2.  For the
     batched workload (fuse "batch") the launches are the stage launches j >= 2
     of the last, eagerly launched super-step, and the figure is their average
-    per launch, like the roofline's.  Writes the JSON that traffic_for reads
-    and returns it."""
+    per launch, like the roofline's.  `variant` is the stencil variant (or
+    batched tile policy) the counter runs used.  Writes the JSON that
+    traffic_for reads and returns it."""
     import csv
 
     def per_dispatch(path, counter):
@@ -138,10 +142,10 @@ def summarize_counters(fetch_csv, write_csv, workload, precision, fuse):
     ff, wf = gib_kib / f_copy, gib_kib / w_copy
     rd, wr = f_k * ff * 1024.0, w_k * wf * 1024.0
     d = {"kernel": KERNEL_NAMES[fuse], "workload": workload, "precision": precision,
-         "kernel_hash": kernel_hash(fuse), "fetch_factor": ff, "write_factor": wf,
+         "kernel_hash": kernel_hash(fuse), "variant": variant, "fetch_factor": ff, "write_factor": wf,
          "read_bytes_per_launch": rd, "write_bytes_per_launch": wr, "bytes_per_launch": rd + wr,
          "dispatches": [nf, nw]}
-    with open(traffic_path(workload, precision, fuse), "w") as fh:
+    with open(traffic_path(workload, precision, fuse, variant), "w") as fh:
         json.dump(d, fh, indent=1)
         fh.write("\n")
     return d
@@ -193,9 +197,13 @@ def bench_batched(args, torch, inputs, rkl, precision="mixed", loop=False):
     stream = rkl.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     if loop:
         big = int(cells.argmax())
-        policy, tuned_ms = rkl.rkl_autotune(plan.handle, big, *plan._tb(big, T0[off[big]:off[big + 1]],
-                                                                        b[3 * off[big]:3 * off[big + 1]]),
-                                            dts[big], 2, stream)
+        if args.variant >= 0:
+            plan.set_variant(args.variant)
+            policy, tuned_ms = args.variant, None
+        else:
+            policy, tuned_ms = rkl.rkl_autotune(plan.handle, big, *plan._tb(big, T0[off[big]:off[big + 1]],
+                                                                            b[3 * off[big]:3 * off[big + 1]]),
+                                                dts[big], 2, stream)
         ptrs = [(rkl.ctypes.c_void_p(T[off[p]:].data_ptr()), rkl.ctypes.c_void_p(b[3 * off[p]:].data_ptr()))
                 for p in range(len(descs))]
 
@@ -203,7 +211,11 @@ def bench_batched(args, torch, inputs, rkl, precision="mixed", loop=False):
             for p in range(len(descs)):
                 s_host[p] = rkl.rkl_superstep(plan.handle, p, ptrs[p][0], ptrs[p][1], dts[p], stream)
     else:
-        policy, tuned_ms = plan.autotune_batched(T0, b, dt, reps=2)   # tile policy by timed search
+        if args.policy >= 0:
+            plan.set_batch_policy(args.policy)
+            policy, tuned_ms = args.policy, None
+        else:
+            policy, tuned_ms = plan.autotune_batched(T0, b, dt, reps=2)   # tile policy by timed search
         plan.graph_capture(T, b, dt, s_out)
 
         def step(s_host):
@@ -251,7 +263,7 @@ def bench_batched(args, torch, inputs, rkl, precision="mixed", loop=False):
         s1 = s_out.cpu().numpy().astype(np.int64)
         achieved = bpc * float((cells * (s1 - 1)).sum()) / (ms / 1e3) / 1e9
         kernel = "batch_stage_kernel (stages j>=2, eager launches)"
-        traffic = traffic_for(args.workload, precision, "batch")   # average bytes per stage j >= 2 launch
+        traffic = traffic_for(args.workload, precision, "batch", policy)   # average bytes per stage j >= 2 launch
     flags = max(plan.query(g)[2] for g in range(0, len(descs), 97))
     sample = None
     if not args.no_cpu_baseline:
@@ -476,6 +488,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="spitzer_256", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", type=int, default=-1, help="kernel variant; -1 = autotune")
+    ap.add_argument("--policy", type=int, default=-1,
+                    help="batched tile policy (patches_2000, patches_2000_fp64); -1 = autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (reference for HBM counters)")
@@ -484,9 +498,13 @@ def main():
     ap.add_argument("--fuse", type=int, default=1, help="stages per launch of the kernel summarized")
     args = ap.parse_args()
     if args.counters_summary:
-        fuse = "batch" if args.workload in ("patches_2000", "patches_2000_fp64") else args.fuse
+        batch = args.workload in ("patches_2000", "patches_2000_fp64")
+        fuse = "batch" if batch else args.fuse
+        v = args.policy if batch else args.variant
+        if v < 0:
+            raise SystemExit("--counters-summary needs the --%s the counter runs used" % ("policy" if batch else "variant"))
         print(json.dumps(summarize_counters(*args.counters_summary, args.workload,
-                                            WORKLOADS[args.workload][1], fuse)))
+                                            WORKLOADS[args.workload][1], fuse, v)))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus %d" % args.gpus,
@@ -556,7 +574,7 @@ def main():
     avg_launch_s = ms / 1e3 / launches
     bytes_per_launch = bytes_per_cs * cells * fuse
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = traffic_for(args.workload, precision, fuse)
+    traffic = traffic_for(args.workload, precision, fuse, variant)
     out = {
         "metric": "cell-stage updates/s",
         "value": cells * stages / sec,
