@@ -42,15 +42,18 @@ namespace rkl {
 // FP64: the hardware estimate y (relative error ~2^-23) corrected once to
 // third order: with e = 1 - x y^2, 1/sqrt(x) = y (1 + e/2 + 3e^2/8 + O(e^3));
 // with e = 1 - x y, 1/x = y (1 + e + e^2 + O(e^3)); the dropped terms are
-// ~2^-66, below the rounding level.
+// ~2^-66, below the rounding level.  sqrt(x) = x / sqrt(x).
 __device__ __forceinline__ float r_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double r_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float r_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double r_rsqrt(double x) {
     const double y = __builtin_amdgcn_rsq(x);
     const double e = fma(-(x * y), y, 1.0);
     return fma(y, e * fma(e, 0.375, 0.5), y);
 }
+// x >= 0: x times the corrected reciprocal root, whose argument is kept at or
+// above 1e-300 so that the estimate stays finite and normal (exactly 0 for
+// x = 0; only x < 1e-300 differs from the square root, by less than 1e-150)
+__device__ __forceinline__ double r_sqrt(double x) { return x * r_rsqrt(fmax(x, 1e-300)); }
 __device__ __forceinline__ float r_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double r_rcp(double x) {
     const double y = __builtin_amdgcn_rcp(x);
