@@ -9,9 +9,11 @@ dt_hyp chosen for s = 16.  Prints one JSON line.
 
 The stencil kernel variant (tile shape, z-chunk, stages per launch) is picked
 by the library's autotuner on the workload's own fields before the timed
-region, unless --variant is given.
+region, unless --variant is given; for the batched patch workloads the tile
+policy likewise, unless --policy is given.
 
-  python bench.py [--steps K] [--warmup W] [--workload NAME] [--variant V] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--variant V] [--policy P]
+                  [--no-cpu-baseline]
 """
 import argparse
 import hashlib
