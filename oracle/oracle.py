@@ -168,7 +168,9 @@ def stages(r: float) -> int:
 
 
 def coeffs(s: int):
-    """(w1, mu, nu, mut, gt) with arrays indexed by stage j = 0..s."""
+    """(w1, mu, nu, mut, gt) with arrays indexed by stage j = 0..s (s >= 2)."""
+    if int(s) < 2:
+        raise ValueError("RKL2 needs s >= 2, got %d" % s)
     arrs = [np.zeros(s + 1) for _ in range(4)]
     w1 = ctypes.c_double()
     load().orc_coeffs(s, ctypes.byref(w1), *[_ptr(a) for a in arrs])
@@ -201,6 +203,8 @@ def face_flux(g: Grid, T, b, cell, d: int) -> float:
 
 def rkl2_fixed(g: Grid, T, b, s: int, tau: float) -> np.ndarray:
     """s RKL2 stages of length tau; returns Y_s (input is not modified)."""
+    if int(s) < 2:
+        raise ValueError("RKL2 needs s >= 2, got %d" % s)
     T = _field(g, T, "T").copy()
     b = _bfield(g, b)
     cg = g.c()

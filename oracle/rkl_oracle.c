@@ -258,8 +258,11 @@ int orc_stages(double r)
  */
 void orc_coeffs(int s, double *w1_out, double *mu, double *nu, double *mut, double *gt)
 {
-    double *bj = (double *)malloc(sizeof(double) * (s + 1));
-    for (int j = 0; j <= s; ++j) {
+    /* RKL2 needs s >= 2 (w1 = 4/(s^2+s-2)); the callers check it.  The b_j
+     * table always holds j = 0..2 so that b_1 is defined whatever s is. */
+    const int nb = s < 2 ? 2 : s;
+    double *bj = (double *)malloc(sizeof(double) * (nb + 1));
+    for (int j = 0; j <= nb; ++j) {
         if (j <= 2) bj[j] = 1.0 / 3.0;
         else bj[j] = ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
     }
