@@ -351,13 +351,32 @@ def cpu_baseline_patches(sample, params, precision, launch):
     return base, acc
 
 
+def _timed_reps(torch, T, T0, fn, args):
+    """args.warmup untimed calls, then args.steps timed ones, each from T0;
+    returns (seconds, summed return values of the timed calls)"""
+    for _ in range(max(args.warmup, 1)):
+        T.copy_(T0)
+        fn()
+    total, count = 0.0, 0
+    for _ in range(args.steps):
+        T.copy_(T0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        count += fn()
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t0
+    return total, count
+
+
 def bench_subcycle(args, torch, inputs, rkl):
     """Explicit sub-cycling (N_sub = ceil(dt_hyp/dt_par) forward-Euler
     sub-steps) of the 256^3 FP64 workload over the dt_hyp that gives its
     RKL2 super-step s = 16, against that super-step (and the RKL1 and AAG
     ones) on the same fields: the measured speed-up of super-time-stepping
     over sub-cycling on this GPU.  One step = one dt_hyp interval; value =
-    cell-sub-steps per second."""
+    cell-sub-steps per second.  Also the speed-up against dt_hyp/dt_par for
+    s = 8, 16, 32, 64 (three timed repetitions each), which the paper's
+    scaling table expects to grow as (dt_hyp/dt_par)^(1/2)."""
     dev = torch.device("cuda:0")
     w = inputs.spitzer_256(device=dev)
     plan = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision="fp64")
@@ -372,18 +391,7 @@ def bench_subcycle(args, torch, inputs, rkl):
                          rkl.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
 
     def timed(fn):
-        for _ in range(max(args.warmup, 1)):
-            T.copy_(T0)
-            fn()
-        total, count = 0.0, 0
-        for _ in range(args.steps):
-            T.copy_(T0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            count += fn()
-            torch.cuda.synchronize()
-            total += time.perf_counter() - t0
-        return total, count
+        return _timed_reps(torch, T, T0, fn, args)
 
     sec_sts, stages = timed(lambda: plan.superstep(T, b, dt))
     plan1 = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision="fp64", scheme="rkl1")
@@ -394,6 +402,16 @@ def bench_subcycle(args, torch, inputs, rkl):
     sec_sub, nsub = timed(lambda: plan.subcycle(T, b, dt))
     ms, launches, _ = rkl.rkl_profile_read(plan.handle, 3)
     rkl.rkl_profile(plan.handle, 0)
+    dtp = plan.dt_par(T0)
+    sweep = []
+    for s_target in (8, 16, 32, 64):
+        dt_k = inputs.midpoint_ratio(s_target) * dtp
+        reps = argparse.Namespace(steps=3, warmup=1)
+        t_rkl2 = _timed_reps(torch, T, T0, lambda: plan.superstep(T, b, dt_k), reps)
+        t_sub = _timed_reps(torch, T, T0, lambda: plan.subcycle(T, b, dt_k), reps)
+        sweep.append({"ratio": dt_k / dtp, "stages": t_rkl2[1] // 3, "substeps": t_sub[1] // 3,
+                      "rkl2_ms": t_rkl2[0] * 1e3 / 3, "subcycle_ms": t_sub[0] * 1e3 / 3,
+                      "speedup": t_sub[0] / t_rkl2[0]})
     plan.close()
     cells = w.cells
     bpc = 40.0                                   # read Y 8 + b 24, write 8
@@ -425,6 +443,7 @@ def bench_subcycle(args, torch, inputs, rkl):
             "rkl1_ms_per_step": sec_rkl1 * 1e3 / args.steps,
             "aag_nu": 0.01, "aag_stages_same_dt": stages_aag // args.steps,
             "aag_ms_per_step": sec_aag * 1e3 / args.steps,
+            "speedup_vs_ratio": sweep,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
