@@ -1,0 +1,87 @@
+"""Seeded random configurations through the C ABI against the oracle: grid
+dimension and (ragged) sizes down to single cells, boundaries per axis,
+limiter, saturation form, conductivity law, kappa_perp ratio, cell widths,
+precision, stencil variant and stage count drawn together, so that
+combinations no hand-written case covers are checked too (for example 2-D
+grids whose unit vectors have a z component).  Bars: FP64 rel-L1 <= 1e-12,
+mixed <= 1e-5, identical stage counts; the flux divergence as well."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import lib_desc, oracle_grid, rel_l1
+from paper_1702_05487_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+NCASES = 60          # cases 48.. are 3-D, periodic, mixed precision, two-stage
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1702_05487_amd import rkl
+    rkl.load(build_if_missing=False)
+    return torch
+
+
+def draw(k):
+    """configuration k: (n, h, ndim, params, precision, variant, s, T, b)"""
+    from paper_1702_05487_amd import rkl
+    rng = np.random.default_rng(1000 + k)
+    fused_case = k >= 48
+    ndim = 3 if fused_case else int(rng.choice([1, 2, 3, 3]))
+    n = [1, 1, 1]
+    for d in range(ndim):
+        n[d] = int(rng.choice([1, 2, 3, 5, 8, 17, 31, 40]) if ndim < 3 else rng.choice([1, 3, 7, 16, 23, 33, 40]))
+    if ndim == 3 and np.prod(n) < 8:
+        n[0] = 9
+    h = tuple(float(v) for v in rng.uniform(0.02, 0.2, 3))
+    sat = int(rng.integers(0, 3))
+    p = dict(inputs.BASE)
+    p.update(limiter=int(rng.integers(0, 2)), saturation=sat, phi=float(rng.choice([0.01, 0.3])),
+             kappa_exp=float(rng.choice([0.0, 2.5, 1.7])), kperp_ratio=float(rng.choice([0.0, 0.01, 0.3])),
+             kappa0=float(rng.uniform(0.5, 2.0)),
+             boundary=tuple(int(rng.random() < 0.3) if d < ndim and not fused_case else 0 for d in range(3)))
+    precision = "mixed" if fused_case or rng.random() < 0.5 else "fp64"
+    periodic3d = ndim == 3 and not any(p["boundary"])
+    fused = fused_case or (precision == "mixed" and periodic3d and rng.random() < 0.5)
+    choices = [v for v in range(rkl.rkl_variant_count()) if rkl.rkl_variant_info(v)[3] == (2 if fused else 1)]
+    variant = int(rng.choice(choices))
+    s = int(rng.integers(2, 13))
+    shape = (n[2], n[1], n[0])
+    T = 1.0 + 0.5 * rng.random(shape)
+    b = inputs.unit_vectors(rng.standard_normal((3,) + shape))
+    return tuple(n), h, ndim, p, precision, variant, s, T, b
+
+
+@pytest.mark.parametrize("k", range(NCASES))
+def test_random_configuration(torch_cuda, k):
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    n, h, ndim, p, precision, variant, s, T, b = draw(k)
+    print("case", k, n, ndim, precision, "variant", variant, "s", s, {x: p[x] for x in
+          ("limiter", "saturation", "kappa_exp", "kperp_ratio", "boundary")}, flush=True)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    bg = b.astype(np.float32) if precision == "mixed" else b
+    bt = torch.float32 if precision == "mixed" else torch.float64
+    g = oracle_grid(n, h, ndim, p)
+    plan = rkl.Plan([lib_desc(n, h, ndim, p)], precision=precision, variant=variant)
+    bd = torch.from_numpy(np.ascontiguousarray(bg)).to(device="cuda:0", dtype=bt)
+    Td = torch.from_numpy(T).to("cuda:0")
+    ref_div = oracle.flux_div(g, T, bg.astype(np.float64))
+    div = plan.flux_div(Td, bd).cpu().numpy()
+    if np.abs(ref_div).max() == 0.0:
+        assert np.all(div == 0.0)
+    else:
+        assert rel_l1(div, ref_div) <= tol
+    dt = inputs.midpoint_ratio(s) * oracle.dt_par(g, T)
+    got_s = plan.superstep(Td, bd, dt)
+    plan.close()
+    ref, s_ref, _ = oracle.superstep(g, T, bg.astype(np.float64), dt)
+    got = Td.cpu().numpy()
+    with np.errstate(invalid="ignore", divide="ignore"):
+        print("  s %d/%d rel-L1 %.3e, change rel-L1 %.3e" % (got_s, s_ref, rel_l1(got, ref), rel_l1(got - T, ref - T)))
+    assert got_s == s_ref == s
+    assert rel_l1(got, ref) <= tol
