@@ -85,3 +85,50 @@ def test_random_configuration(torch_cuda, k):
         print("  s %d/%d rel-L1 %.3e, change rel-L1 %.3e" % (got_s, s_ref, rel_l1(got, ref), rel_l1(got - T, ref - T)))
     assert got_s == s_ref == s
     assert rel_l1(got, ref) <= tol
+
+
+@pytest.mark.parametrize("k", range(12))
+def test_random_batched_plan(torch_cuda, k):
+    """a batched plan of 2-10 patches of mixed dimension, size and
+    boundaries (shared limiter, saturation and conductivity law), each with
+    its own dt_hyp, one captured-graph super-step, every patch against the
+    oracle"""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    rng = np.random.default_rng(5000 + k)
+    precision = "mixed" if k % 2 else "fp64"
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    p0 = dict(inputs.BASE, limiter=int(rng.integers(0, 2)), saturation=int(rng.integers(0, 3)),
+              phi=0.05, kappa_exp=float(rng.choice([0.0, 2.5, 1.7])), kperp_ratio=float(rng.choice([0.0, 0.05])))
+    descs, cases = [], []
+    for _ in range(int(rng.integers(2, 11))):
+        ndim = int(rng.integers(1, 4))
+        n = [1, 1, 1]
+        for d in range(ndim):
+            n[d] = int(rng.integers(1, 40 if ndim < 3 else 20))
+        p = dict(p0, boundary=tuple(int(rng.random() < 0.4) if d < ndim else 0 for d in range(3)))
+        h = tuple(float(v) for v in rng.uniform(0.02, 0.2, 3))
+        shape = (n[2], n[1], n[0])
+        T = 1.0 + 0.5 * rng.random(shape)
+        b = inputs.unit_vectors(rng.standard_normal((3,) + shape))
+        s = int(rng.integers(2, 16))
+        descs.append(lib_desc(tuple(n), h, ndim, p))
+        cases.append((tuple(n), h, ndim, p, T, b, s))
+    plan = rkl.Plan(descs, precision=precision, smax=16)
+    bdt = np.float32 if precision == "mixed" else np.float64
+    T = torch.from_numpy(np.concatenate([c[4].ravel() for c in cases])).to("cuda:0")
+    b = torch.from_numpy(np.concatenate([c[5].astype(bdt).ravel() for c in cases])).to("cuda:0")
+    dts = [inputs.midpoint_ratio(c[6]) * oracle.dt_par(oracle_grid(c[0], c[1], c[2], c[3]), c[4]) for c in cases]
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
+    s_out = torch.zeros(len(cases), dtype=torch.int32, device="cuda:0")
+    plan.graph_capture(T, b, dt, s_out)
+    plan.graph_launch()
+    got, s_got = T.cpu().numpy(), s_out.cpu().numpy()
+    off = plan.offsets()
+    plan.close()
+    for i, (n, h, ndim, p, T0, b0, s) in enumerate(cases):
+        ref, s_ref, _ = oracle.superstep(oracle_grid(n, h, ndim, p), T0, b0.astype(bdt).astype(np.float64), dts[i])
+        err = rel_l1(got[off[i]:off[i + 1]].reshape(T0.shape), ref)
+        print("plan %d patch %d %s ndim %d bc %s s %d/%d rel-L1 %.3e" % (k, i, n, ndim, p["boundary"], s_got[i], s_ref, err))
+        assert s_got[i] == s_ref == s, i
+        assert err <= tol, i
