@@ -132,3 +132,43 @@ def test_random_batched_plan(torch_cuda, k):
         print("plan %d patch %d %s ndim %d bc %s s %d/%d rel-L1 %.3e" % (k, i, n, ndim, p["boundary"], s_got[i], s_ref, err))
         assert s_got[i] == s_ref == s, i
         assert err <= tol, i
+
+
+@pytest.mark.parametrize("method", ["rkl1", "aag", "subcycle"])
+@pytest.mark.parametrize("k", range(16))
+def test_random_configuration_other_integrators(torch_cuda, k, method):
+    """the same random configurations with RKL1 (dt_hyp for s stages), AAG
+    (nu = 0.1, dt_hyp = 5 dt_par) and explicit sub-cycling (dt_hyp = 7.3
+    dt_par), against the oracle's same integrator"""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    n, h, ndim, p, precision, variant, s, T, b = draw(k)
+    if rkl.rkl_variant_info(variant)[3] == 2:
+        variant = 0                      # two-stage launches are an RKL2 form
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    bg = b.astype(np.float32) if precision == "mixed" else b
+    bt = torch.float32 if precision == "mixed" else torch.float64
+    g = oracle_grid(n, h, ndim, p)
+    plan = rkl.Plan([lib_desc(n, h, ndim, p)], precision=precision, variant=variant,
+                    scheme="rkl1" if method == "rkl1" else "rkl2")
+    bd = torch.from_numpy(np.ascontiguousarray(bg)).to(device="cuda:0", dtype=bt)
+    Td = torch.from_numpy(T).to("cuda:0")
+    b64 = bg.astype(np.float64)
+    dtp = oracle.dt_par(g, T)
+    if method == "rkl1":
+        dt = ((s - 0.5) ** 2 + (s - 0.5)) / 2.0 * dtp
+        c = plan.superstep(Td, bd, dt)
+        ref, c_ref, _ = oracle.superstep_rkl1(g, T, b64, dt)
+        assert c == s
+    elif method == "aag":
+        c = plan.aag(Td, bd, 5.0 * dtp, 0.1)
+        ref, c_ref = oracle.aag_superstep(g, T, b64, 5.0 * dtp, 0.1)
+    else:
+        c = plan.subcycle(Td, bd, 7.3 * dtp)
+        ref, c_ref = oracle.subcycle(g, T, b64, 7.3 * dtp)
+        assert c == 8
+    plan.close()
+    got = Td.cpu().numpy()
+    print("case %d %s %s: count %d/%d rel-L1 %.3e" % (k, method, precision, c, c_ref, rel_l1(got, ref)))
+    assert c == c_ref
+    assert rel_l1(got, ref) <= tol
