@@ -394,6 +394,9 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
     }
     e = hipMemcpy(p->coef, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->state, 0, sizeof(GridState) * ngrids);
+    // the set-up above is ordered on the legacy stream; finish it so that the
+    // caller's first launch on any stream sees it
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { free_plan(p); return hipfail(e, "plan upload"); }
     if (ngrids > 1 && o.scheme == RKL_RKL2) {
         std::string why;
