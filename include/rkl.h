@@ -113,7 +113,8 @@ typedef struct {
  * device current at this call is the plan's device: every later call on the
  * plan (except rkl_destroy, which switches to it) returns RKL_EINVAL while
  * another device is current.  opt may be NULL (RKL_FP64, default variant,
- * default smax).
+ * default smax).  Synchronises the device before returning, so the plan is
+ * ready for launches on any stream.
  * Errors: RKL_EINVAL for a bad descriptor or option (including a two-stage
  * variant for a plan that cannot use it), RKL_ENOMEM, RKL_EDEVICE.
  */
