@@ -77,3 +77,35 @@ def test_side_stream_gives_the_same_bits(torch_cuda, precision):
     for k in ref:
         assert np.array_equal(np.asarray(ref[k]), np.asarray(got[k])), k
     assert ref["s"] == 9 and ref["nsub"] == 6
+
+
+def test_two_plans_on_two_threads(torch_cuda):
+    """two plans used at once from two host threads, each on its own
+    stream (the library keeps no state outside a plan; rkl_last_error is per
+    thread): the same bits as one after the other"""
+    torch = torch_cuda
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_1702_05487_amd import rkl
+
+    def work(seed):
+        n = (28, 20, 16)
+        p = dict(inputs.SPITZER_MC_SAT, phi=0.05)
+        T0 = torch.from_numpy(inputs.noisy_temperature(n, seed, kmax=4)).to("cuda:0")
+        b = torch.from_numpy(inputs.tangled_b(n, seed + 1, kmax=4)).to("cuda:0")
+        torch.cuda.synchronize()
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            plan = rkl.Plan([lib_desc(n, (0.04, 0.05, 0.06), 3, p)])
+            T = T0.clone()
+            dt = inputs.midpoint_ratio(11) * plan.dt_par(T)
+            ss = [plan.superstep(T, b, dt) for _ in range(4)]
+            side.synchronize()
+            plan.close()
+        return ss, T.cpu().numpy()
+
+    seq = [work(s) for s in (21, 31)]
+    with ThreadPoolExecutor(2) as ex:
+        par = list(ex.map(work, (21, 31)))
+    for (s1, t1), (s2, t2) in zip(seq, par):
+        assert s1 == s2
+        assert np.array_equal(t1, t2)
