@@ -436,3 +436,27 @@ def test_kernel_symmetries(torch_cuda, precision, tol):
           " ".join("%.1e" % v for v in gaps))
     # mixed: the three FP32 direction sums are added in another order
     assert max(gaps) <= tol
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_full_size_conserves_energy(torch_cuda, precision, bar):
+    """256^3 periodic workload, two super-steps: every face flux enters its
+    two cells with opposite signs, so the sum of T is conserved up to
+    rounding -- |sum dT| / sum |dT| within the bar (FP64: rounding of the
+    stage sums; mixed: FP32 face fluxes)"""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    w = inputs.spitzer_256(fields=False)
+    T0 = inputs.noisy_temperature(w.n, 2, device="cuda:0")
+    b = inputs.tangled_b(w.n, 1, device="cuda:0")
+    b = b.float() if precision == "mixed" else b.double()
+    plan = rkl.Plan([lib_desc(w.n, w.h, 3, w.params)], precision=precision)
+    T = T0.clone()
+    dt = w.ratio * plan.dt_par(T)
+    for _ in range(2):
+        assert plan.superstep(T, b, dt) >= 15
+    plan.close()
+    d = (T - T0)
+    drift = abs(float(d.sum())) / float(d.abs().sum())
+    print("%s: sum |dT| %.3e, |sum dT| / sum |dT| %.3e" % (precision, float(d.abs().sum()), drift))
+    assert drift <= bar
