@@ -1,0 +1,53 @@
+"""bench.py on the GPU, run as a child process with one timed step: the
+one JSON line it prints carries every field of the benchmark contract
+(metric, value, unit, steps, timing, dtype, config, roofline with its peak
+and fraction, and the oracle's CPU baseline with its core count)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def run_bench(*args):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                       capture_output=True, text=True, timeout=600, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [x for x in r.stdout.splitlines() if x.startswith("{")]
+    assert len(lines) == 1, r.stdout[-2000:]
+    return json.loads(lines[0])
+
+
+def check_line(d, steps):
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline"):
+        assert k in d, k
+    assert d["metric"] == "cell-stage updates/s" and d["unit"] == "cell-stage/s"
+    assert d["n_gpus"] == 1 and d["steps"] == steps and d["higher_is_better"] is True
+    assert d["value"] > 1e9 and d["ms_per_step"] > 0
+    assert d["data"] == "synthetic" and d["vs_baseline"] is None
+    assert "workload" in d["config"]
+    r = d["roofline"]
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert 0 < r["achieved"] < r["peak"] and r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    assert r["traffic"] is None or r["traffic"] > 0
+
+
+def test_default_line():
+    d = run_bench("--steps", "1", "--warmup", "0")
+    check_line(d, 1)
+    assert d["dtype"] == "f64" and d["config"]["grid"] == [256, 256, 256]
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0 and cb["unit"] == "cell-stage/s"
+    assert d["accuracy"]["rel_l1"] <= 1e-12
+
+
+def test_batched_line():
+    d = run_bench("--workload", "patches_2000", "--steps", "1", "--warmup", "0", "--no-cpu-baseline")
+    check_line(d, 1)
+    assert d["config"]["patches"] == 2000 and 0 <= d["config"]["tile_policy"]
