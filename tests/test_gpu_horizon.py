@@ -11,11 +11,16 @@ MC-limited multi-stage update amplifies such noise at a few cells (limiter
 switches), so that is the scale any FP32 flux arithmetic is held to.
 Patches whose stage count at some super-step differs between the runs
 (dt_hyp is fixed, s follows T_max, and a patch near an integer crossing may
-take either) are counted and left out of the comparison."""
+take either) are counted and left out of the comparison.
+
+The 64^2 Gaussian pulse is small enough for the oracle itself: its five
+super-steps (dt_hyp = 50 dt_par, s = 14 each) run in FP64 and mixed
+precision against five oracle super-steps, every cell compared."""
 import numpy as np
 import pytest
 
-from helpers import lib_desc
+import oracle
+from helpers import lib_desc, oracle_grid, rel_l1
 from paper_1702_05487_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -109,3 +114,36 @@ def test_patches_over_the_whole_horizon(torch_cuda):
     assert (~same).sum() <= 0.02 * len(same)
     assert err <= max(1e-5, 10 * err_n)
     assert linf <= 10 * linf_n
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gaussian_pulse_over_its_horizon(torch_cuda, precision):
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    w = inputs.gaussian_pulse_2d(64)
+    bg = w.b.astype(np.float32) if precision == "mixed" else w.b
+    g = oracle_grid(w.n, w.h, w.ndim, w.params)
+    plan = rkl.Plan([lib_desc(w.n, w.h, w.ndim, w.params)], precision=precision)
+    T = torch.from_numpy(np.ascontiguousarray(w.T)).to("cuda:0")
+    b = torch.from_numpy(np.ascontiguousarray(bg)).to("cuda:0")
+    ref, tol = w.T.copy(), (1e-12 if precision == "fp64" else 1e-5)
+    for step in range(w.steps):
+        dt = w.ratio * oracle.dt_par(g, ref)
+        assert plan.dt_par(T) == oracle.dt_par(g, ref)
+        s = plan.superstep(T, b, dt)
+        ref, s_ref, _ = oracle.superstep(g, ref, bg.astype(np.float64), dt)
+        got = T.cpu().numpy()
+        print("gaussian2d_64 %s super-step %d: s %d/%d, rel-L1 %.3e, Linf %.3e"
+              % (precision, step + 1, s, s_ref, rel_l1(got, ref), float(np.abs(got - ref).max())), flush=True)
+        assert s == s_ref == 14
+        assert rel_l1(got, ref) <= tol
+    plan.close()
+    # kappa is uniform and b fixed: the sum of T is conserved over the horizon
+    # (FP64 to rounding; mixed precision to the FP32 rounding of each cell's
+    # divergence, far below 1e-6 of the total change)
+    drift = abs(got.sum() - w.T.sum())
+    print("sum of T drifts by %.3e (total change %.3e)" % (drift, np.abs(got - w.T).sum()))
+    if precision == "fp64":
+        assert drift <= 1e-12 * np.abs(w.T).sum()
+    else:
+        assert drift <= 1e-6 * np.abs(got - w.T).sum()
