@@ -91,7 +91,7 @@ def test_batched_equals_single_grid_calls(torch_cuda):
 
 @pytest.mark.skip(reason="the single persistent launch with per-grid stage-dependency counters "
                          "(work queues, agent-scope release/acquire between workgroups) did not "
-                         "finish on the MI355X box; its cause is not shown, so that code path is "
+                         "finish on the MI355X; its cause is not shown, so that code path is "
                          "removed and the batched super-step uses one launch per stage")
 def test_persistent_equals_per_stage_launches():
     pass
