@@ -578,12 +578,13 @@ def main():
     T.copy_(T0)
     torch.cuda.synchronize()
     rkl.rkl_profile(plan.handle, 1)
-    stages = 0
+    per_step = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        stages += plan.superstep(T, bdev, dt)
+        per_step.append(plan.superstep(T, bdev, dt))
     torch.cuda.synchronize()
+    stages = sum(per_step)
     sec = time.perf_counter() - t0
     ms, launches, cell_stages = rkl.rkl_profile_read(plan.handle, fuse)
     rkl.rkl_profile(plan.handle, 0)
@@ -610,7 +611,7 @@ def main():
         "dtype": "f64" if precision == "fp64" else "f32 flux + f64 recurrence",
         "data": "synthetic",
         "config": {
-            "workload": w.name.replace("_" + w.precision, "_" + precision), "grid": list(w.n), "stages": s_last, "precision": precision,
+            "workload": w.name.replace("_" + w.precision, "_" + precision), "grid": list(w.n), "stages": s_last, "stages_per_step": per_step, "precision": precision,
             "kappa_par": "T^2.5", "kperp_ratio": w.params["kperp_ratio"],
             "limiter": "MC" if w.params["limiter"] else "mean",
             "saturation": ["off", "central", "upwind"][w.params["saturation"]],

@@ -42,6 +42,10 @@ def test_default_line():
     d = run_bench("--steps", "1", "--warmup", "0")
     check_line(d, 1)
     assert d["dtype"] == "f64" and d["config"]["grid"] == [256, 256, 256]
+    # value = cells x the stages of the timed super-steps / their wall time
+    per = d["config"]["stages_per_step"]
+    assert len(per) == 1 and per[0] == d["config"]["stages"] and 15 <= per[0] <= 16
+    assert d["value"] == pytest.approx(256 ** 3 * sum(per) / (d["ms_per_step"] * d["steps"] / 1e3), rel=1e-9)
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0 and cb["unit"] == "cell-stage/s"
     assert d["accuracy"]["rel_l1"] <= 1e-12
