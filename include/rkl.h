@@ -165,11 +165,27 @@ rkl_status rkl_dt_par(rkl_plan_t plan, int32_t grid, const double *T, double *dt
  * and s from dt_hyp = dt_par (s^2+s)/2 rounded as for RKL2 (s >= 1; s = 1 is
  * one forward-Euler step).
  * For a super-step with no host synchronisation (HIP graph capture), use
- * rkl_superstep_batched on a plan of one grid with smax near the expected s;
- * it gives the same bits as this entry point.
+ * rkl_superstep_async; it gives the same bits as this entry point.
  */
 rkl_status rkl_superstep(rkl_plan_t plan, int32_t grid, double *T, const void *b,
                          double dt_hyp, int32_t *s_out, void *stream);
+
+/*
+ * rkl_superstep_async: the RKL2 super-step of rkl_superstep (Appendix A, Eq.
+ * rkl2scheme; s from Eq. RKL-s) with no host synchronisation and no
+ * allocation, so it can be captured in a HIP graph.  s is computed on the
+ * device and never read back: the call enqueues one reduction, one finalize
+ * launch and s_cap stage launches; stage j does nothing when j > s.  If
+ * s > s_cap, every stage does nothing (T unchanged) and the grid is flagged
+ * RKL_FLAG_STAGES (rkl_query).  s_out: device int32 (may be NULL) receiving
+ * s.  s_cap in [2, the plan's smax] (RKL_EINVAL otherwise); RKL2 plans only
+ * (RKL_EINVAL for RKL1).  Uses the plan's one-stage stencil variant (variant
+ * 0 while a two-stage variant is selected); the same bits as rkl_superstep
+ * for the same variant.  An empty stage launch costs a few microseconds, so
+ * s_cap should be near the largest s expected.
+ */
+rkl_status rkl_superstep_async(rkl_plan_t plan, int32_t grid, double *T, const void *b, double dt_hyp,
+                               int32_t s_cap, int32_t *s_out, void *stream);
 
 /*
  * rkl_subcycle: explicit sub-cycling of the conduction operator over dt_hyp
@@ -295,6 +311,20 @@ rkl_status rkl_batch_policy_info(int32_t policy, int32_t *half_rows, int32_t *ti
 rkl_status rkl_set_batch_policy(rkl_plan_t plan, int32_t policy);
 rkl_status rkl_autotune_batched(rkl_plan_t plan, const double *T, const void *b, const double *dt_hyp,
                                 int32_t reps, int32_t *best_policy, double *best_ms, void *stream);
+
+/*
+ * rkl_stream: a bandwidth probe of the HBM path (not part of the method):
+ * one coalesced sweep over `bytes` bytes with a given per-lane width, for
+ * measuring what the stencil's loads can reach and for calibrating HBM
+ * counters.  mode 0: copy src -> dst in 8-byte elements (the width of the
+ * FP64 stencil loads); mode 1: copy in 16-byte elements; mode 3: copy in
+ * 4-byte elements (the FP32 unit-vector loads); mode 2: read src in 8-byte
+ * elements and write one double per 1024 elements read to dst (a read-only
+ * sweep; dst holds bytes/8192 doubles).  bytes: a positive multiple of 16;
+ * src and dst 16-byte aligned device pointers that do not overlap.
+ * Enqueued on `stream`, no synchronisation.
+ */
+rkl_status rkl_stream(const void *src, void *dst, int64_t bytes, int32_t mode, void *stream);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *rkl_last_error(void);

@@ -87,7 +87,7 @@ def build(force: bool = False) -> str:
     if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call([
-            "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+            "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
             "-fPIC", "-shared", "-o", tmp, _SRC, "-lm",
         ])
         os.replace(tmp, _LIB)
@@ -103,6 +103,10 @@ def load():
         lib = ctypes.CDLL(os.environ.get("RKL_ORACLE_LIB") or build())
         dp = ctypes.POINTER(ctypes.c_double)
         gp = ctypes.POINTER(_CGrid)
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
+        lib.orc_get_threads.argtypes = []
+        lib.orc_get_threads.restype = ctypes.c_int
         lib.orc_mc.argtypes = [ctypes.c_double, ctypes.c_double]
         lib.orc_mc.restype = ctypes.c_double
         lib.orc_stages.argtypes = [ctypes.c_double]
@@ -157,6 +161,18 @@ def _bfield(g: Grid, b):
     if b.shape != (3,) + g.shape:
         raise ValueError(f"b: shape {b.shape} != {(3,) + g.shape}")
     return b
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's cell loops (1 = serial, the default).  The
+    result is the same bits for any count; returns the count in effect."""
+    lib = load()
+    lib.orc_set_threads(int(n))
+    return lib.orc_get_threads()
+
+
+def threads() -> int:
+    return load().orc_get_threads()
 
 
 def mc(a: float, b: float) -> float:

@@ -42,12 +42,31 @@
  *   and b, as in the exact-solution or outflow ghosts the paper's tests use
  *   at non-periodic edges).
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math), so every
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no fast-math), so every
  * a*b+c rounds twice, exactly as written.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the cell loops.  Every cell's value is computed on its own
+ * from inputs that the loop does not write, so the result is the same bits
+ * for any thread count; the default is one thread (serial). */
+static int orc_threads = 1;
+
+void orc_set_threads(int n) { orc_threads = n < 1 ? 1 : n; }
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return orc_threads;
+#else
+    return 1;
+#endif
+}
 
 /* Grid and physics parameters.  Layout of every field: [n2][n1][n0], axis 0
  * fastest.  b is three such arrays back to back (component-major). */
@@ -201,6 +220,7 @@ double orc_face_flux(const orc_grid *g, const double *T, const double *b, int i,
 void orc_flux_div(const orc_grid *g, const double *T, const double *b, double *out)
 {
     const double fac = (g->gamma - 1.0) / g->rho;
+#pragma omp parallel for collapse(2) num_threads(orc_threads) schedule(static) if (orc_threads > 1)
     for (int k = 0; k < g->n[2]; ++k)
         for (int j = 0; j < g->n[1]; ++j)
             for (int i = 0; i < g->n[0]; ++i) {

@@ -11,16 +11,17 @@
 #include "../../include/rkl.h"
 #include "rkl_internal.h"
 #include "rkl_batch.h"
+#include "rkl_host.h"
 
 using namespace rkl;
 
 static thread_local std::string g_err;
 
-static rkl_status fail(rkl_status st, const std::string& msg) {
+rkl_status rkl::fail(rkl_status st, const std::string& msg) {
     g_err = msg;
     return st;
 }
-static rkl_status hipfail(hipError_t e, const char* what) {
+rkl_status rkl::hipfail(hipError_t e, const char* what) {
     return fail(RKL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 #define HIPCHECK(call, what)                   \
@@ -74,11 +75,8 @@ static void prof_clear(rkl_plan_s* p) {
 }
 
 // ---------------------------------------------------------------------------
-// RKL2 coefficients (Appendix A): for s stages, w1 = 4/(s^2+s-2),
-// b_j = (j^2+j-2)/(2j(j+1)) (b_0 = b_1 = b_2 = 1/3), a_j = 1 - b_j,
-// mut_1 = b_1 w1, mu_j = (2j-1)/j b_j/b_{j-1}, nu_j = -(j-1)/j b_j/b_{j-2},
-// mut_j = mu_j w1, gt_j = -a_{j-1} mut_j.  Row j of s holds
-// {mu_j, nu_j, 1 - mu_j - nu_j, mut_j, gt_j} at 5 (s(s+1)/2 + j).
+// RKL2 coefficients (Appendix A, rkl2_row in rkl_internal.h): row j of s
+// holds {mu_j, nu_j, 1 - mu_j - nu_j, mut_j, gt_j} at 5 (s(s+1)/2 + j).
 // RKL1 (Sec. 3.3: P_s(1 + w1 z), w1 = 2/(s^2+s), Legendre recursion): mut_1 =
 // w1; mu_j = (2j-1)/j, nu_j = -(j-1)/j, mut_j = mu_j w1, and no Y0 or tau
 // M(Y0) term (1 - mu_j - nu_j = 0, gt_j = 0).
@@ -101,29 +99,12 @@ static std::vector<double> coefficient_table(int smax, int scheme) {
         }
         return t;
     }
-    std::vector<double> bj(smax + 1);
-    for (int j = 0; j <= smax; ++j)
-        bj[j] = j <= 2 ? 1.0 / 3.0 : ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
-    for (int s = 2; s <= smax; ++s) {
-        const double w1 = 4.0 / ((double)s * s + s - 2.0);
-        double* row = &t[5 * ((size_t)s * (s + 1) / 2)];
-        row[5 * 1 + 3] = bj[1] * w1;
-        for (int j = 2; j <= s; ++j) {
-            const double mu = (2.0 * j - 1.0) / j * bj[j] / bj[j - 1];
-            const double nu = -(j - 1.0) / j * bj[j] / bj[j - 2];
-            const double mut = mu * w1;
-            double* r = row + 5 * j;
-            r[0] = mu;
-            r[1] = nu;
-            r[2] = 1.0 - mu - nu;
-            r[3] = mut;
-            r[4] = -(1.0 - bj[j - 1]) * mut;
-        }
-    }
+    for (int s = 2; s <= smax; ++s)
+        for (int j = 1; j <= s; ++j) rkl2_row(s, j, &t[5 * ((size_t)s * (s + 1) / 2 + j)]);
     return t;
 }
 
-static bool validate(const rkl_grid_desc& g, std::string& why) {
+bool rkl::validate(const rkl_grid_desc& g, std::string& why) {
     char buf[160];
     if (g.ndim < 1 || g.ndim > 3) { why = "ndim must be 1, 2 or 3"; return false; }
     for (int d = 0; d < 3; ++d) {
@@ -151,7 +132,7 @@ static bool validate(const rkl_grid_desc& g, std::string& why) {
     return true;
 }
 
-static GridConst make_const(const rkl_grid_desc& g, int scheme) {
+GridConst rkl::make_const(const rkl_grid_desc& g, int scheme) {
     GridConst c;
     c.n0 = g.n[0];
     c.n1 = g.n[1];
@@ -445,11 +426,11 @@ static rkl_status check_grid(rkl_plan_t p, int32_t g) {
 
 // min/max reduction of T and the finalize step for grid g
 static rkl_status reduce_and_finalize(rkl_plan_t p, int32_t g, const double* T, double dt_hyp, int mode,
-                                      int32_t* s_dev, hipStream_t st) {
+                                      int32_t* s_dev, hipStream_t st, int smax = 0) {
     const int64_t N = p->off[g + 1] - p->off[g];
     const int nb = reduce_blocks(N);
     HIPCHECK(launch_reduce(T, N, p->partials, nb, st), "reduce launch");
-    HIPCHECK(launch_finalize(p->partials, nb, p->gc[g], dt_hyp, mode, p->state + g, s_dev, p->smax, st),
+    HIPCHECK(launch_finalize(p->partials, nb, p->gc[g], dt_hyp, mode, p->state + g, s_dev, smax ? smax : p->smax, st),
              "finalize launch");
     return RKL_OK;
 }
@@ -563,6 +544,33 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
     }
     if (S == 1)   // RKL1 with one stage: Y1 was written next to T (stage 1 reads T around each cell)
         HIPCHECK(hipMemcpyAsync(T, bufs[0], sizeof(double) * n, hipMemcpyDeviceToDevice, s), "result copy");
+    return RKL_OK;
+}
+
+rkl_status rkl_superstep_async(rkl_plan_t p, int32_t g, double* T, const void* b, double dt_hyp,
+                               int32_t s_cap, int32_t* s_out, void* stream) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
+    if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
+    if (p->scheme != RKL_RKL2) return fail(RKL_EINVAL, "rkl_superstep_async implements RKL2 only");
+    if (s_cap < 2 || s_cap > p->smax)
+        return fail(RKL_EINVAL, "s_cap must be in [2, smax=" + std::to_string(p->smax) + "]");
+    hipStream_t s = (hipStream_t)stream;
+    // s on the device; stages beyond it (and every stage, if s > s_cap) return at once
+    st = reduce_and_finalize(p, g, T, dt_hyp, 0, s_out, s, s_cap);
+    if (st != RKL_OK) return st;
+    const GridConst& gc = p->gc[g];
+    Variant v = variant_get(p->variant);
+    if (v.fuse != 1) v = variant_get(0);   // routed launches are one stage each
+    const size_t rs = p->precision == RKL_MIXED ? sizeof(float) : sizeof(double);
+    void* M = (char*)p->MY0 + rs * p->off[g];
+    const Route r{p->Ya + p->off[g], p->Yb + p->off[g], s_cap, 0};
+    for (int j = 1; j <= s_cap; ++j)
+        HIPCHECK(launch_stage(p->precision, v, gc, j == 1 ? 1 : 2, j, nullptr, nullptr, nullptr, M, M, T, b,
+                              p->state + g, p->coef, s, 0.0, &r),
+                 "routed stage launch");
     return RKL_OK;
 }
 

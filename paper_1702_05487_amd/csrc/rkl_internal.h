@@ -75,6 +75,37 @@ __device__ inline GridState finalize_state(const GridConst& g, double mx, double
     return o;
 }
 
+// Row j (0 <= j <= s) of the RKL2 coefficient table of an s-stage super-step
+// (Appendix A): w1 = 4/(s^2+s-2), b_j = (j^2+j-2)/(2j(j+1)) (b_0 = b_1 =
+// b_2 = 1/3), a_j = 1 - b_j; row 1 holds mut_1 = b_1 w1 in r[3]; rows
+// j >= 2 hold {mu_j, nu_j, 1 - mu_j - nu_j, mut_j, gt_j} with
+// mu_j = (2j-1)/j b_j/b_{j-1}, nu_j = -(j-1)/j b_j/b_{j-2}, mut_j = mu_j w1,
+// gt_j = -a_{j-1} mut_j; row 0 is zero.  The host table of a plan and the
+// device rows of the allocation-free super-step both come from here
+// (IEEE operations, no contraction), so they hold the same bits.
+__host__ __device__ inline double rkl2_bj(int j) {
+#pragma clang fp contract(off)
+    return j <= 2 ? 1.0 / 3.0 : ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
+}
+__host__ __device__ inline void rkl2_row(int s, int j, double* r) {
+#pragma clang fp contract(off)
+    for (int i = 0; i < 5; ++i) r[i] = 0.0;
+    const double w1 = 4.0 / ((double)s * s + s - 2.0);
+    if (j == 1) {
+        r[3] = rkl2_bj(1) * w1;
+    } else if (j >= 2) {
+        const double bj = rkl2_bj(j), bj1 = rkl2_bj(j - 1), bj2 = rkl2_bj(j - 2);
+        const double mu = (2.0 * j - 1.0) / j * bj / bj1;
+        const double nu = -(j - 1.0) / j * bj / bj2;
+        const double mut = mu * w1;
+        r[0] = mu;
+        r[1] = nu;
+        r[2] = 1.0 - mu - nu;
+        r[3] = mut;
+        r[4] = -(1.0 - bj1) * mut;
+    }
+}
+
 // Kernel variants of the single-grid stencil: tile shape, z-chunk length and
 // stages per launch (1, or 2 for the fused kernel).
 struct Variant {
@@ -86,14 +117,34 @@ Variant variant_get(int v);
 // Launchers (enqueue only; return the HIP error of the launch).
 hipError_t launch_reduce(const double* T, int64_t N, double* partials, int nblocks, hipStream_t st);
 int reduce_blocks(int64_t N);
+// coef_rows (may be NULL): for a super-step (mode 0, RKL2) whose stage count
+// s is in [2, smax], rows 0..s of its coefficient table (rkl2_row, 5 doubles
+// each; room for smax + 1 rows) are written there on the device.
 hipError_t launch_finalize(const double* partials, int nblocks, const GridConst& gc, double dt_hyp,
-                           int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st);
+                           int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st,
+                           double* coef_rows = nullptr);
+// Device-side routing of an RKL2 stage (for launch sequences that do not
+// know s on the host): with s the grid's device-side stage count, stage j
+// does nothing when j > s or s is outside [2, s_cap]; otherwise it reads
+// Y_{j-1} and Y_{j-2} from, and writes Y_j to, T (Y_0 and Y_s), A (odd j)
+// or B (even j).  coef_flat: the coefficient rows of the current s start at
+// `coef` (row j at 5 j) instead of the table of all s (row of s at
+// 5 s(s+1)/2).
+struct Route {
+    double* A;
+    double* B;
+    int s_cap;
+    int coef_flat;
+};
 // kind: 0 flux divergence into Yout, 1 first stage, 2 stage j >= 2,
-// 3 explicit sub-step Yout = Yin + tau L(Yin) with sub_scale = -tau (gamma-1)/rho
+// 3 explicit sub-step Yout = Yin + tau L(Yin) with sub_scale = -tau (gamma-1)/rho.
+// With `route` set (kinds 1 and 2), Yin, Ym2 and Yout are chosen on the
+// device as described above and the ones passed are ignored.
 hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind, int stage,
                         const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
-                        const double* coef, hipStream_t st, double sub_scale = 0.0);
+                        const double* coef, hipStream_t st, double sub_scale = 0.0,
+                        const Route* route = nullptr);
 // stages j and j+1 (2 <= j, j+1 < s) in one launch, RKL_MIXED and 3-D grids
 // only; Yj and Yj1 must alias none of Yin, Ym2, Y0
 hipError_t launch_fused2(Variant v, const GridConst& gc, int stage, const double* Yin, const double* Ym2,

@@ -65,10 +65,13 @@ hipError_t launch_reduce(const double* T, int64_t N, double* partials, int nbloc
     return hipGetLastError();
 }
 
-// mode 0: super-step (computes s); mode 1: flux_div / dt_par only (s = 0)
+// mode 0: super-step (computes s); mode 1: flux_div / dt_par only (s = 0).
+// Every lane ends the butterfly with the grid's extrema, so all 64 lanes
+// form the same state; lane 0 stores it and the lanes share the rows of the
+// coefficient table (coef_rows, RKL2 super-steps with 2 <= s <= smax).
 __global__ __launch_bounds__(64) void finalize_kernel(const double* __restrict__ part, int nb, GridConst g,
                                                       double dt_hyp, int mode, GridState* st,
-                                                      int32_t* s_out, int smax) {
+                                                      int32_t* s_out, int smax, double* coef_rows) {
     double mx = -INFINITY, mn = INFINITY, bad = 0.0;
     for (int i = threadIdx.x; i < nb; i += 64) {
         mx = fmax(mx, part[3 * i]);
@@ -80,15 +83,23 @@ __global__ __launch_bounds__(64) void finalize_kernel(const double* __restrict__
         mn = fmin(mn, __shfl_xor(mn, off));
         bad = fmax(bad, __shfl_xor(bad, off));
     }
-    if (threadIdx.x != 0) return;
     const GridState o = finalize_state(g, mx, mn, bad != 0.0, dt_hyp, mode, smax);
+    if (coef_rows && mode == 0 && g.scheme == 0 && o.s >= 2 && o.s <= smax) {
+        for (int j = threadIdx.x; j <= o.s; j += 64) {
+            double r[5];
+            rkl2_row(o.s, j, r);
+            for (int i = 0; i < 5; ++i) coef_rows[5 * j + i] = r[i];
+        }
+    }
+    if (threadIdx.x != 0) return;
     *st = o;
     if (s_out) *s_out = o.s;
 }
 
 hipError_t launch_finalize(const double* partials, int nblocks, const GridConst& gc, double dt_hyp,
-                           int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st) {
-    finalize_kernel<<<1, 64, 0, st>>>(partials, nblocks, gc, dt_hyp, mode, state, s_out, smax);
+                           int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st,
+                           double* coef_rows) {
+    finalize_kernel<<<1, 64, 0, st>>>(partials, nblocks, gc, dt_hyp, mode, state, s_out, smax, coef_rows);
     return hipGetLastError();
 }
 
@@ -103,6 +114,7 @@ struct StageLaunch {
     int kmode;
     double fac;
     double sub_scale;    // kind 3: -tau_sub (gamma-1)/rho
+    Route route;         // route.A != NULL: Yin, Ym2, Yout chosen on the device (kinds 1, 2)
 };
 
 // FIX3: 3-D grid, tile shape fixed at compile time (run_tile's CBX, CBY)
@@ -133,7 +145,21 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
         a.scale = P.sub_scale;
     } else {
         const int s = st->s;
-        const double* cf = P.coef + 5 * ((size_t)s * (s + 1) / 2 + P.stage);
+        if (P.route.A) {
+            // the stage sequence was launched up to s_cap without knowing s
+            if (P.stage > s || s < 2 || s > P.route.s_cap) return;   // uniform over the grid
+            const int j = P.stage;
+            double* T = a.Yout;   // the caller's T (Y_0, and Y_s)
+            double* Yj = (j & 1) ? P.route.A : P.route.B;
+            if (j == 1) {
+                a.Yin = T;
+            } else {
+                a.Yin = ((j - 1) & 1) ? P.route.A : P.route.B;
+                a.Ym2 = j == 2 ? T : Yj;   // Y_{j-2} sits where Y_j goes
+            }
+            a.Yout = j == s ? T : Yj;
+        }
+        const double* cf = P.coef + 5 * (P.route.coef_flat ? (size_t)P.stage : (size_t)s * (s + 1) / 2 + P.stage);
         a.mu = cf[0];
         a.nu = cf[1];
         a.omn = cf[2];
@@ -187,7 +213,7 @@ static hipError_t launch_prec(const StageLaunch& P, int nblocks, int bx, int by,
 hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind, int stage,
                         const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
-                        const double* coef, hipStream_t st, double sub_scale) {
+                        const double* coef, hipStream_t st, double sub_scale, const Route* route) {
     StageLaunch P;
     TileArgs& a = P.t;
     a.Yin = Yin;
@@ -225,6 +251,15 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
     P.kmode = gc.kmode;
     P.fac = gc.fac;
     P.sub_scale = sub_scale;
+    P.route = Route{nullptr, nullptr, 0, 0};
+    if (route) {
+        // routed stages: Yout carries the caller's T to the kernel
+        if ((kind != 1 && kind != 2) || !route->A || !route->B || !Yout) return hipErrorInvalidValue;
+        P.route = *route;
+        a.Yin = Yout;
+        a.Ym2 = Yout;
+        a.Y0 = Yout;
+    }
     const int64_t nb = (int64_t)P.ntx * P.nty * nzc;
     if (nb <= 0 || nb > 0x7fffffff) return hipErrorInvalidValue;
     const bool lim = gc.limiter != 0;

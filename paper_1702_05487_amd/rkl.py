@@ -25,11 +25,11 @@ RKL_FLAG_NONPOS, RKL_FLAG_NONFINITE, RKL_FLAG_STAGES = 1, 2, 4
 
 EXPORTS = [
     "rkl_plan", "rkl_destroy", "rkl_grid_offset", "rkl_flux_div", "rkl_dt_par",
-    "rkl_superstep", "rkl_superstep_batched", "rkl_graph_capture", "rkl_graph_launch",
+    "rkl_superstep", "rkl_superstep_async", "rkl_superstep_batched", "rkl_graph_capture", "rkl_graph_launch",
     "rkl_query", "rkl_variant_count", "rkl_variant_info", "rkl_set_variant", "rkl_last_error",
     "rkl_profile", "rkl_profile_read", "rkl_autotune",
     "rkl_batch_policy_count", "rkl_batch_policy_info", "rkl_set_batch_policy", "rkl_autotune_batched",
-    "rkl_subcycle", "rkl_aag",
+    "rkl_subcycle", "rkl_aag", "rkl_stream",
 ]
 
 
@@ -89,6 +89,7 @@ def load(build_if_missing: bool = True):
         "rkl_flux_div": (i32, [vp, i32, vp, vp, vp, vp]),
         "rkl_dt_par": (i32, [vp, i32, vp, P(dbl), vp]),
         "rkl_superstep": (i32, [vp, i32, vp, vp, dbl, P(i32), vp]),
+        "rkl_superstep_async": (i32, [vp, i32, vp, vp, dbl, i32, vp, vp]),
         "rkl_superstep_batched": (i32, [vp, vp, vp, vp, vp, vp]),
         "rkl_graph_capture": (i32, [vp, vp, vp, vp, vp, vp]),
         "rkl_graph_launch": (i32, [vp, vp]),
@@ -106,6 +107,7 @@ def load(build_if_missing: bool = True):
         "rkl_autotune_batched": (i32, [vp, vp, vp, vp, i32, P(i32), P(dbl), vp]),
         "rkl_subcycle": (i32, [vp, i32, vp, vp, dbl, i64, P(i64), vp]),
         "rkl_aag": (i32, [vp, i32, vp, vp, dbl, dbl, i32, P(i32), vp]),
+        "rkl_stream": (i32, [vp, vp, i64, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -153,6 +155,10 @@ def rkl_superstep(plan, grid, T_ptr, b_ptr, dt_hyp, stream):
     return s.value
 
 
+def rkl_superstep_async(plan, grid, T_ptr, b_ptr, dt_hyp, s_cap, s_ptr, stream):
+    _check(load().rkl_superstep_async(plan, grid, T_ptr, b_ptr, float(dt_hyp), int(s_cap), s_ptr, stream))
+
+
 def rkl_subcycle(plan, grid, T_ptr, b_ptr, dt_hyp, max_sub, stream):
     n = ctypes.c_int64()
     _check(load().rkl_subcycle(plan, grid, T_ptr, b_ptr, float(dt_hyp), int(max_sub), ctypes.byref(n), stream))
@@ -196,6 +202,23 @@ def rkl_variant_info(v):
 
 def rkl_set_variant(plan, v):
     _check(load().rkl_set_variant(plan, v))
+
+
+def rkl_stream(src_ptr, dst_ptr, nbytes, mode, stream):
+    _check(load().rkl_stream(src_ptr, dst_ptr, int(nbytes), int(mode), stream))
+
+
+def stream_probe(src, dst, mode=0):
+    """One rkl_stream sweep over the torch tensor src (mode 0/1/3: copy into
+    dst, same size; mode 2: read-only, dst holds src.nbytes // 8192 doubles)."""
+    import torch
+    for t, name in ((src, "src"), (dst, "dst")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("%s must be a contiguous CUDA (HIP) tensor" % name)
+    need = src.nbytes // 8192 * 8 if mode == 2 else src.nbytes
+    if dst.nbytes < need:
+        raise ValueError("dst holds %d bytes, %d needed" % (dst.nbytes, need))
+    rkl_stream(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), src.nbytes, mode, _stream())
 
 
 def rkl_last_error():
@@ -321,6 +344,14 @@ class Plan:
         """Advance T in place by one super-step; returns the stage count."""
         tp, bp = self._tb(grid, T, b)
         return rkl_superstep(self.handle, grid, tp, bp, dt_hyp, _stream())
+
+    def superstep_async(self, T, b, dt_hyp, s_cap, s_out=None, grid=0):
+        """Advance T in place by one super-step without host synchronisation
+        (s_cap stage launches; s lands in the int32 device tensor s_out)."""
+        import torch
+        tp, bp = self._tb(grid, T, b)
+        sp = None if s_out is None else _dev_ptr(s_out, torch.int32, 1, "s_out")
+        rkl_superstep_async(self.handle, grid, tp, bp, dt_hyp, s_cap, sp, _stream())
 
     def subcycle(self, T, b, dt_hyp, max_sub=1 << 20, grid=0):
         """Explicit sub-cycling over dt_hyp (T in place); returns the number of sub-steps."""

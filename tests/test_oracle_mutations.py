@@ -20,7 +20,7 @@ def _caught(item, src, workdir):
     os.makedirs(d)
     with open(os.path.join(d, "m.c"), "w") as f:
         f.write(src.replace(old, new))
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
                            "-o", os.path.join(d, "m.so"), os.path.join(d, "m.c"), "-lm"])
     env = dict(os.environ, RKL_ORACLE_LIB=os.path.join(d, "m.so"))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu"]
