@@ -3,9 +3,16 @@
 
 One step = one full RKL2 super-step (temperature reduction, dt_par and stage
 count on the device, then s stencil/stage launches) over the whole grid.
-Default workload: 256^3 periodic grid, FP64, tangled k^-11/3 field, kappa_par
-= T^2.5, kappa_perp = 1e-3 kappa_par, MC-limited transverse gradients,
-dt_hyp chosen for s = 16.  Prints one JSON line.
+Default workload (the largest single-GPU configuration): a 768^3 periodic
+grid in mixed precision (FP32 flux arithmetic, FP64 stage recurrence),
+tangled k^-11/3 field, kappa_par = T^2.5, kappa_perp = 1e-3 kappa_par,
+MC-limited transverse gradients, central saturated flux (phi = 0.3),
+dt_hyp chosen for s = 32, 20 super-steps.  The same JSON line carries the
+comparison legs on the same fields and patches (the plain FP64 form of the
+768^3 grid; the 2000 uneven patches as the mixed batched graph and as a
+plain FP64 loop of one super-step per patch), the error against the oracle
+over the workload's whole horizon on the same fields sampled at 64^3, and
+the oracle's own rate (serial and on all host cores).  Prints one JSON line.
 
 The stencil kernel variant (tile shape, z-chunk, stages per launch) is picked
 by the library's autotuner on the workload's own fields before the timed
@@ -13,7 +20,7 @@ region, unless --variant is given; for the batched patch workloads the tile
 policy likewise, unless --policy is given.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--variant V] [--policy P]
-                  [--no-cpu-baseline]
+                  [--no-cpu-baseline] [--no-legs]
 """
 import argparse
 import hashlib
@@ -41,7 +48,8 @@ WORKLOADS = {
     "spitzer_256_subcycle": ("spitzer_256", "fp64"),   # explicit sub-cycling over the same dt_hyp
 }
 KERNEL_SOURCES = {
-    1: ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_kernels.hip"],
+    1: ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_stage.h",
+        "paper_1702_05487_amd/csrc/rkl_kernels.hip"],
     2: ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_fused.h",
         "paper_1702_05487_amd/csrc/rkl_fused.hip"],
     "batch": ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_batch.hip"],
@@ -90,35 +98,40 @@ def traffic_for(name, precision, fuse, variant):
     return d.get("bytes_per_launch")
 
 
-def summarize_counters(fetch_csv, write_csv, workload, precision, fuse, variant):
+def summarize_counters(read_csv, write_csv, workload, precision, fuse, variant):
     """HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc
-    runs of this script with --copy-calibration (FETCH_SIZE, then
-    WRITE_SIZE; KiB per dispatch).  Each counter is scaled by the factor that
-    makes it read 1 GiB for the plain 1 GiB device copy that starts the
-    calibration run.  Stage-1 launches (the first stencil launch after each finalize
-    launch) are left out: the measured kernel is stages j >= 2.  For the
-    batched workload (fuse "batch") the launches are the stage launches j >= 2
-    of the last, eagerly launched super-step, and the figure is their average
-    per launch, like the roofline's.  `variant` is the stencil variant (or
-    batched tile policy) the counter runs used.  Writes the JSON that
-    traffic_for reads and returns it."""
+    runs of this script with --copy-calibration: the read run collects
+    TCC_EA0_RDREQ_32B_sum, TCC_EA0_RDREQ_64B_sum and TCC_EA0_RDREQ_128B_sum
+    (read requests to HBM by size), the write run TCC_EA0_WRREQ_sum and
+    TCC_EA0_WRREQ_64B_sum (write requests, 64 B or else 32 B); bytes are the
+    request counts times their sizes.  The calibration run starts with the
+    library's streaming copy of 1 GiB (rkl_stream, 8-byte lanes), whose
+    counted bytes must come out at 1 GiB each way; the factors that would make
+    them so are recorded as a check, not applied.  Stage-1 launches (the
+    first stencil launch after each finalize launch) are left out: the
+    measured kernel is stages j >= 2.  For the batched workload (fuse
+    "batch") the launches are the stage launches j >= 2 of the last, eagerly
+    launched super-step, and the figure is their average per launch, like
+    the roofline's.  `variant` is the stencil variant (or batched tile
+    policy) the counter runs used.  Writes the JSON that traffic_for reads
+    and returns it."""
     import csv
 
-    def per_dispatch(path, counter):
+    def per_dispatch(path, weights):
         out = {}
         for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] != counter:
+            w = weights.get(r["Counter_Name"])
+            if w is None:
                 continue
             d = int(r["Dispatch_Id"])
             name, v = out.get(d, (r["Kernel_Name"], 0.0))
-            out[d] = (name, v + float(r["Counter_Value"]))
+            out[d] = (name, v + w * float(r["Counter_Value"]))
         return out
 
     def measured(disp):
-        # the calibration copy is the run's first device copy
-        copies = [disp[d][1] for d in sorted(disp) if "copyBuffer" in disp[d][0]]
+        copies = [disp[d][1] for d in sorted(disp) if "copy_kernel" in disp[d][0]]
         if not copies:
-            raise SystemExit("no copy-calibration dispatch in the counter file")
+            raise SystemExit("no calibration copy (rkl_stream) dispatch in the counter file")
         vals, after_finalize = [], False
         if fuse == "batch":
             # the last (eager) batched super-step: its stage launches after the
@@ -138,13 +151,14 @@ def summarize_counters(fetch_csv, write_csv, workload, precision, fuse, variant)
             raise SystemExit("no %s dispatch in the counter file" % KERNEL_NAMES[fuse])
         return sum(vals) / len(vals), copies[0], len(vals)
 
-    f_k, f_copy, nf = measured(per_dispatch(fetch_csv, "FETCH_SIZE"))
-    w_k, w_copy, nw = measured(per_dispatch(write_csv, "WRITE_SIZE"))
-    gib_kib = float(1 << 20)
-    ff, wf = gib_kib / f_copy, gib_kib / w_copy
-    rd, wr = f_k * ff * 1024.0, w_k * wf * 1024.0
+    # read requests by size; write requests: 64 B ones, the rest 32 B
+    rd, r_copy, nf = measured(per_dispatch(read_csv, {"TCC_EA0_RDREQ_32B_sum": 32.0, "TCC_EA0_RDREQ_64B_sum": 64.0,
+                                                      "TCC_EA0_RDREQ_128B_sum": 128.0}))
+    wr, w_copy, nw = measured(per_dispatch(write_csv, {"TCC_EA0_WRREQ_sum": 32.0, "TCC_EA0_WRREQ_64B_sum": 32.0}))
+    gib = float(1 << 30)
     d = {"kernel": KERNEL_NAMES[fuse], "workload": workload, "precision": precision,
-         "kernel_hash": kernel_hash(fuse), "variant": variant, "fetch_factor": ff, "write_factor": wf,
+         "kernel_hash": kernel_hash(fuse), "variant": variant,
+         "calibration_copy_read_over_1GiB": r_copy / gib, "calibration_copy_write_over_1GiB": w_copy / gib,
          "read_bytes_per_launch": rd, "write_bytes_per_launch": wr, "bytes_per_launch": rd + wr,
          "dispatches": [nf, nw]}
     with open(traffic_path(workload, precision, fuse, variant), "w") as fh:
@@ -213,11 +227,15 @@ def bench_batched(args, torch, inputs, rkl, precision="mixed", loop=False):
             for p in range(len(descs)):
                 s_host[p] = rkl.rkl_superstep(plan.handle, p, ptrs[p][0], ptrs[p][1], dts[p], stream)
     else:
+        npol = rkl.rkl_batch_policy_count()
         if args.policy >= 0:
-            plan.set_batch_policy(args.policy)
+            # --policy: tile policy + launch mode x the policy count
+            plan.set_batch_policy(args.policy % npol)
+            plan.set_batch_mode(args.policy // npol)
             policy, tuned_ms = args.policy, None
         else:
-            policy, tuned_ms = plan.autotune_batched(T0, b, dt, reps=2)   # tile policy by timed search
+            # tile policy and launch mode by timed search
+            policy, tuned_ms = plan.autotune_batched(T0, b, dt, reps=2)
         plan.graph_capture(T, b, dt, s_out)
 
         def step(s_host):
@@ -260,12 +278,20 @@ def bench_batched(args, torch, inputs, rkl, precision="mixed", loop=False):
         torch.cuda.synchronize()
         rkl.rkl_profile(plan.handle, 1)
         plan.superstep_batched(T, b, dt, s_out)
-        ms, launches, _ = rkl.rkl_profile_read(plan.handle, 1)
+        persistent = policy // rkl.rkl_batch_policy_count() == 1
+        ms, launches, _ = rkl.rkl_profile_read(plan.handle, 4 if persistent else 1)
         rkl.rkl_profile(plan.handle, 0)
         s1 = s_out.cpu().numpy().astype(np.int64)
-        achieved = bpc * float((cells * (s1 - 1)).sum()) / (ms / 1e3) / 1e9
-        kernel = "batch_stage_kernel (stages j>=2, eager launches)"
-        traffic = traffic_for(args.workload, precision, "batch", policy)   # average bytes per stage j >= 2 launch
+        if persistent:
+            # one launch holds every stage: stage 1 reads T and b and writes
+            # Y1 and tau M(Y0) (mixed 32 B, FP64 40 B per cell), stages j >= 2 as above
+            b1 = 32.0 if precision == "mixed" else 40.0
+            achieved = float((cells * (b1 + bpc * (s1 - 1))).sum()) / (ms / 1e3) / 1e9
+            kernel = "batch_persistent_kernel (all stages, eager launch)"
+        else:
+            achieved = bpc * float((cells * (s1 - 1)).sum()) / (ms / 1e3) / 1e9
+            kernel = "batch_stage_kernel (stages j>=2, eager launches)"
+        traffic = None if persistent else traffic_for(args.workload, precision, "batch", policy)
     flags = max(plan.query(g)[2] for g in range(0, len(descs), 97))
     sample = None
     if not args.no_cpu_baseline:
@@ -286,8 +312,11 @@ def bench_batched(args, torch, inputs, rkl, precision="mixed", loop=False):
         launch = "host loop, one rkl_superstep per patch"
         tile = {"variant": policy, "tile": list(rkl.rkl_variant_info(policy)[:3])}
     else:
-        launch = "hipGraph replay, one launch per stage"
-        tile = {"tile_policy": policy, "policy_half_rows_tile_z": list(rkl.rkl_batch_policy_info(policy))}
+        npol = rkl.rkl_batch_policy_count()
+        launch = ("hipGraph replay: reduce, schedule and one persistent launch" if policy // npol == 1
+                  else "hipGraph replay, one launch per stage")
+        tile = {"tile_policy": policy % npol, "launch_mode": policy // npol,
+                "policy_half_rows_tile_z": list(rkl.rkl_batch_policy_info(policy % npol))}
     out = {
         "metric": "cell-stage updates/s",
         "value": cell_stages / sec,
@@ -468,53 +497,184 @@ def host_cpu():
     return "%s, %d threads visible" % (model, len(os.sched_getaffinity(0)))
 
 
-def cpu_baseline(w, T0, b, dt, precision, torch, rkl):
-    """The oracle, untuned, on a bounded sample of the same workload: one
-    super-step of length dt of a 256 x 256 x 16 periodic slab cut from the
-    same fields (host arrays T0 [16][256][256], b [3][16][256][256]), on one
-    host core.  The library then runs the same slab (as its own periodic
-    grid, in the plan's precision) and its error against the oracle is
-    returned with the baseline."""
+HORIZON_N = (64, 64, 64)
+
+
+def horizon_check(w, precision, torch, rkl, threads):
+    """The oracle's rate and the library's error over the workload's whole
+    horizon, on the workload's own continuous fields sampled at 64^3 (same
+    parameters, dt_hyp ratio and number of super-steps).
+
+    cpu_baseline: the oracle (untuned) timed serially on one host core for
+    the first super-step, and on `threads` cores (its OpenMP loop over the
+    cells; the same result bits, checked) for the whole horizon.
+    accuracy: the library in the workload's precision against that oracle
+    run at every super-step; mixed precision also against the oracle fed the
+    FP64 unit vectors (the FP64 problem), which adds the rounding of b to
+    FP32.  The library's FP64 form runs beside it as a check."""
     import numpy as np
     import oracle
-    nz, m = 16, 256
-    T = np.ascontiguousarray(T0)
-    b = np.ascontiguousarray(b)
-    g = oracle.Grid(n=(m, m, nz), h=w.h, ndim=3, **w.params)
+    from paper_1702_05487_amd import inputs
+    n = HORIZON_N
+    T0 = inputs.noisy_temperature(n, 2)
+    b = inputs.tangled_b(n, 1)
+    h = tuple(1.0 / v for v in n)
+    g = oracle.Grid(n=n, h=h, ndim=3, **w.params)
+    bq = b.astype(np.float32).astype(np.float64) if precision == "mixed" else b
+
+    def lib(prec):
+        plan = rkl.Plan([rkl.grid_desc(n, h, ndim=3, **w.params)], precision=prec)
+        T = torch.from_numpy(T0.copy()).to("cuda:0")
+        bd = torch.from_numpy(b).to("cuda:0", dtype=torch.float32 if prec == "mixed" else torch.float64)
+        dt = w.ratio * plan.dt_par(T)
+        outs, ss = [], []
+        for _ in range(w.steps):
+            ss.append(plan.superstep(T, bd, dt))
+            outs.append(T.cpu().numpy())
+        plan.close()
+        return outs, ss, dt
+
+    got, s_lib, dt = lib(precision)
+    got64, s_lib64, dt64 = lib("fp64") if precision == "mixed" else (got, s_lib, dt)
+    assert dt64 == dt == w.ratio * oracle.dt_par(g, T0)
+
+    def orc(bb, nthreads):
+        oracle.set_threads(nthreads)
+        t0 = time.perf_counter()
+        T, outs, ss = T0, [], []
+        for _ in range(w.steps):
+            T, s, _ = oracle.superstep(g, T, bb, dt)
+            outs.append(T)
+            ss.append(s)
+        return outs, ss, time.perf_counter() - t0
+
+    oracle.set_threads(1)
     t0 = time.perf_counter()
-    ref, s, _ = oracle.superstep(g, T, b, dt)
-    sec = time.perf_counter() - t0
-    cells = m * m * nz
-    base = {"value": cells * s / sec, "unit": "cell-stage/s", "cores": 1, "kind": "oracle",
-            "sample": "one %d-stage super-step of a %dx%dx%d periodic slab cut from the same fields "
-                      "(%.1f s serial)" % (s, m, m, nz, sec), "host": host_cpu()}
-    plan = rkl.Plan([rkl.grid_desc((m, m, nz), w.h, ndim=3, **w.params)], precision=precision)
-    Td = torch.from_numpy(T).to("cuda:0")
-    bd = torch.from_numpy(b).to("cuda:0", dtype=torch.float32 if precision == "mixed" else torch.float64)
-    s_gpu = plan.superstep(Td, bd, dt)
-    got = Td.cpu().numpy()
-    plan.close()
-    acc = {"rel_l1": float(np.abs(got - ref).sum() / np.abs(ref).sum()),
-           "linf": float(np.abs(got - ref).max()),
-           "rel_l1_change": float(np.abs(got - ref).sum() / np.abs(ref - T).sum()),
-           "stages": [int(s_gpu), int(s)],
-           "sample": "the same slab and super-step, library (%s) vs oracle (FP64)" % precision}
+    first, s1, _ = oracle.superstep(g, T0, bq, dt)
+    sec1 = time.perf_counter() - t0
+    ref, s_ref, sec_all = orc(bq, threads)
+    used = oracle.threads()
+    ref64, s_ref64, _ = orc(b, threads) if precision == "mixed" else (ref, s_ref, 0.0)
+    oracle.set_threads(1)
+    assert np.array_equal(first, ref[0]), "threaded oracle differs from serial"
+    cells = int(np.prod(n))
+
+    def rel(a, r):
+        return float(np.abs(a - r).sum() / np.abs(r).sum())
+
+    base = {"value": cells * sum(s_ref) / sec_all, "unit": "cell-stage/s", "cores": used, "kind": "oracle",
+            "sample": "%d super-steps (%d stages) of the workload's fields sampled at %dx%dx%d, all cells "
+                      "(%.1f s on %d threads)" % (w.steps, sum(s_ref), n[0], n[1], n[2], sec_all, used),
+            "serial": {"value": cells * s1 / sec1, "cores": 1,
+                       "sample": "the first of those super-steps on one core (%.1f s)" % sec1},
+            "host": host_cpu()}
+    e64 = [rel(a, r) for a, r in zip(got64, ref64)]
+    within = 0
+    while within < len(e64) and e64[within] <= 1e-12:
+        within += 1
+    acc = {"kind": "whole horizon against the oracle, every cell (%dx%dx%d, %d super-steps)"
+                   % (n[0], n[1], n[2], w.steps),
+           "stages": {"library": s_lib, "oracle": s_ref},
+           "first_step": {"rel_l1": rel(got[0], ref[0]), "linf": float(np.abs(got[0] - ref[0]).max()),
+                          "rel_l1_change": float(np.abs(got[0] - ref[0]).sum() / np.abs(ref[0] - T0).sum())},
+           "rel_l1_per_step": [rel(a, r) for a, r in zip(got, ref)],
+           "rel_l1": rel(got[-1], ref[-1]),
+           "linf": float(np.abs(got[-1] - ref[-1]).max()),
+           # how far the FP64 library (operations in another order, same
+           # arithmetic) drifts from the oracle over the same horizon: the
+           # problem's own amplification of rounding differences
+           "fp64_library": {"stages": s_lib64, "rel_l1_per_step": e64,
+                            "steps_within_1e-12": within}}
+    if precision == "mixed":
+        acc["reference"] = "oracle fed the same FP32-rounded unit vectors (arithmetic only)"
+        acc["against_fp64_problem"] = {
+            "reference": "oracle fed the FP64 unit vectors", "stages_oracle": s_ref64,
+            "rel_l1_per_step": [rel(a, r) for a, r in zip(got, ref64)],
+            "rel_l1": rel(got[-1], ref64[-1]), "linf": float(np.abs(got[-1] - ref64[-1]).max())}
     return base, acc
+
+
+def horizon_errors_from_tests():
+    """Per-configuration horizon errors measured by the GPU tests (committed
+    summary), if any."""
+    path = os.path.join(ROOT, "profiles", "horizon_errors.json")
+    try:
+        return json.load(open(path))
+    except (OSError, ValueError):
+        return None
+
+
+def run_grid(torch, rkl, w, T0, b, precision, steps, warmup, variant=-1, one_stage_only=False):
+    """One timed single-grid run: plan, variant (autotuned unless given),
+    `warmup` untimed and `steps` timed super-steps from T0, the dominant
+    kernel's launches timed with HIP events.  Returns a dict."""
+    plan = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision=precision)
+    T = T0.clone()
+    dt = w.ratio * plan.dt_par(T)     # the library's own dt_par of the initial field
+    stream = rkl.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    tuned_ms = None
+    if variant < 0:
+        variant, tuned_ms = rkl.rkl_autotune(plan.handle, 0, *plan._tb(0, T, b), dt, 2, stream)
+        if one_stage_only and rkl.rkl_variant_info(variant)[3] != 1:
+            raise RuntimeError("autotuner picked a fused variant for a one-stage-only run")
+    else:
+        plan.set_variant(variant)
+    tile = rkl.rkl_variant_info(variant)
+    fuse = tile[3]
+    for _ in range(warmup):
+        plan.superstep(T, b, dt)
+    T.copy_(T0)
+    torch.cuda.synchronize()
+    rkl.rkl_profile(plan.handle, 1)
+    per_step = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        per_step.append(plan.superstep(T, b, dt))
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    ms, launches, cell_stages = rkl.rkl_profile_read(plan.handle, fuse)
+    rkl.rkl_profile(plan.handle, 0)
+    plan.close()
+    del T
+    bpc = bytes_per_cell_stage(precision, fuse)
+    avg = ms / 1e3 / launches
+    achieved = bpc * w.cells * fuse / avg / 1e9
+    return {"value": w.cells * sum(per_step) / sec, "ms_per_step": sec * 1e3 / steps, "stages_per_step": per_step,
+            "dt_hyp": dt, "variant": variant, "tile": list(tile[:3]), "stages_per_launch": fuse,
+            "autotuned_ms_per_step": tuned_ms, "kernel": "%s (stages j>=2)" % KERNEL_NAMES[fuse],
+            "bytes_per_cell_stage": bpc, "avg_launch_ms": avg * 1e3, "launches": launches,
+            "achieved": achieved, "kernel_cell_stage_per_s": cell_stages / (ms / 1e3)}
+
+
+def batched_leg(torch, inputs, rkl, workload, steps, warmup):
+    """One of the 2000-patch forms, timed, without its CPU baseline."""
+    a = argparse.Namespace(workload=workload, steps=steps, warmup=warmup, variant=-1, policy=-1,
+                           no_cpu_baseline=True)
+    _, precision = WORKLOADS[workload]
+    d = bench_batched(a, torch, inputs, rkl, precision, workload.endswith("_loop"))
+    r = d["roofline"]
+    return {"value": d["value"], "ms_per_step": d["ms_per_step"], "steps": steps,
+            "stages_min": d["config"]["stages_min"], "stages_max": d["config"]["stages_max"],
+            "launch": d["config"]["launch"], "kernel": r["kernel"], "achieved_GBs": r["achieved"],
+            "frac": r["frac"], "traffic": r["traffic"]}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="spitzer_256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="fused_768", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", type=int, default=-1, help="kernel variant; -1 = autotune")
     ap.add_argument("--policy", type=int, default=-1,
                     help="batched tile policy (patches_2000, patches_2000_fp64); -1 = autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="leave out the comparison legs of the default workload (FP64 form, patches)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="first run one plain 1 GiB device-to-device copy (reference for HBM counters)")
-    ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="first run the library's 1 GiB streaming copy (reference for HBM counters)")
+    ap.add_argument("--counters-summary", nargs=2, metavar=("READ_CSV", "WRITE_CSV"),
                     help="write the traffic JSON of --workload/--variant from two rocprofv3 counter files")
     ap.add_argument("--fuse", type=int, default=1, help="stages per launch of the kernel summarized")
     args = ap.parse_args()
@@ -532,18 +692,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    import oracle
     from paper_1702_05487_amd import inputs, rkl
 
     builder, precision = WORKLOADS[args.workload]
     rkl.load(build_if_missing=True)
     if args.copy_calibration:
+        # the reference dispatch of the HBM counters: the library's streaming
+        # copy of 1 GiB with 8-byte lanes (rkl_stream)
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        rkl.stream_probe(src, dst, 0)
         torch.cuda.synchronize()
         del src, dst
     if builder == "patch_set":
@@ -555,85 +715,78 @@ def main():
         return
     dev = torch.device("cuda:0")
     w = getattr(inputs, builder)(device=dev)       # fields generated on the GPU
-    plan = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision=precision)
     T0, w.T = w.T, None
-    bdev = w.b.to(dtype=torch.float32 if precision == "mixed" else torch.float64)
-    w.b = None
-    T = T0.clone()
-    dt = w.ratio * plan.dt_par(T)     # the library's own dt_par of the initial field
-    cells = w.cells
-    tuned_ms = None
-    if args.variant >= 0:
-        plan.set_variant(args.variant)
-        variant = args.variant
-    else:
-        variant, tuned_ms = rkl.rkl_autotune(plan.handle, 0, *plan._tb(0, T, bdev), dt, 2,
-                                             rkl.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-    tile = rkl.rkl_variant_info(variant)
-    fuse = tile[3]
-    bytes_per_cs = bytes_per_cell_stage(precision, fuse)
-
-    for _ in range(args.warmup):
-        plan.superstep(T, bdev, dt)
-    T.copy_(T0)
-    torch.cuda.synchronize()
-    rkl.rkl_profile(plan.handle, 1)
-    per_step = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        per_step.append(plan.superstep(T, bdev, dt))
-    torch.cuda.synchronize()
-    stages = sum(per_step)
-    sec = time.perf_counter() - t0
-    ms, launches, cell_stages = rkl.rkl_profile_read(plan.handle, fuse)
-    rkl.rkl_profile(plan.handle, 0)
-    s_last = plan.query()[0]
-    # host copies of a 256 x 256 x 16 slab for the CPU baseline
-    T0_host = T0[:16, :256, :256].cpu().numpy()
-    b_host = bdev[:, :16, :256, :256].double().cpu().numpy()
-
-    avg_launch_s = ms / 1e3 / launches
-    bytes_per_launch = bytes_per_cs * cells * fuse
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = traffic_for(args.workload, precision, fuse, variant)
+    b64, w.b = w.b, None
+    bdev = b64.to(dtype=torch.float32 if precision == "mixed" else torch.float64)
+    if precision == "mixed" and (args.no_legs or args.workload != "fused_768"):
+        del b64
+        b64 = None
+    r = run_grid(torch, rkl, w, T0, bdev, precision, args.steps, args.warmup, args.variant)
+    del bdev
+    torch.cuda.empty_cache()
+    traffic = traffic_for(args.workload, precision, r["stages_per_launch"], r["variant"])
     out = {
         "metric": "cell-stage updates/s",
-        "value": cells * stages / sec,
+        "value": r["value"],
         "unit": "cell-stage/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec * 1e3 / args.steps,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if precision == "fp64" else "f32 flux + f64 recurrence",
         "data": "synthetic",
         "config": {
-            "workload": w.name.replace("_" + w.precision, "_" + precision), "grid": list(w.n), "stages": s_last, "stages_per_step": per_step, "precision": precision,
+            "workload": w.name.replace("_" + w.precision, "_" + precision), "grid": list(w.n),
+            "stages": r["stages_per_step"][-1], "stages_per_step": r["stages_per_step"], "precision": precision,
             "kappa_par": "T^2.5", "kperp_ratio": w.params["kperp_ratio"],
             "limiter": "MC" if w.params["limiter"] else "mean",
             "saturation": ["off", "central", "upwind"][w.params["saturation"]],
-            "variant": variant, "tile": list(tile[:3]), "stages_per_launch": fuse,
-            "autotuned_ms_per_step": tuned_ms,
+            "variant": r["variant"], "tile": r["tile"], "stages_per_launch": r["stages_per_launch"],
+            "autotuned_ms_per_step": r["autotuned_ms_per_step"],
         },
         "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-            "kernel": "%s (stages j>=2)" % KERNEL_NAMES[fuse], "bytes_per_cell_stage": bytes_per_cs,
-            "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
-            "kernel_cell_stage_per_s": cell_stages / (ms / 1e3),
+            "bound": "hbm", "achieved": r["achieved"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": r["achieved"] / PEAK_HBM_GBS, "traffic": traffic,
+            "kernel": r["kernel"], "bytes_per_cell_stage": r["bytes_per_cell_stage"],
+            "avg_launch_ms": r["avg_launch_ms"], "launches": r["launches"],
+            "kernel_cell_stage_per_s": r["kernel_cell_stage_per_s"],
         },
     }
-    plan.close()
-    del T, T0, bdev
+    if args.workload == "fused_768" and not args.no_legs:
+        # the plain FP64 form on the same fields (one-stage kernels), then the patches
+        legs = {}
+        bf = b64.to(torch.float64)
+        del b64
+        f = run_grid(torch, rkl, w, T0, bf, "fp64", min(args.steps, 5), 1, one_stage_only=True)
+        del bf
+        torch.cuda.empty_cache()
+        legs["fp64_plain_768"] = {k: f[k] for k in ("value", "ms_per_step", "stages_per_step", "variant", "tile",
+                                                     "kernel", "achieved", "avg_launch_ms")}
+        legs["fp64_plain_768"]["frac"] = f["achieved"] / PEAK_HBM_GBS
+        legs["fp64_plain_768"]["dt_hyp_same"] = f["dt_hyp"] == r["dt_hyp"]
+        legs["mixed_over_fp64_768"] = r["value"] / f["value"]
+        del T0
+        torch.cuda.empty_cache()
+        legs["patches_2000_mixed_batched"] = batched_leg(torch, inputs, rkl, "patches_2000", 10, 2)
+        legs["patches_2000_fp64_loop"] = batched_leg(torch, inputs, rkl, "patches_2000_fp64_loop", 2, 1)
+        legs["patches_mixed_batched_over_fp64_loop"] = (legs["patches_2000_mixed_batched"]["value"]
+                                                        / legs["patches_2000_fp64_loop"]["value"])
+        legs["patches_mixed_batched_over_fp64_plain_768"] = (legs["patches_2000_mixed_batched"]["value"]
+                                                             / legs["fp64_plain_768"]["value"])
+        out["legs"] = legs
+    else:
+        del T0
     torch.cuda.empty_cache()
     ceil = copy_ceiling(torch)
     out["roofline"]["copy_GBs"] = ceil
-    out["roofline"]["frac_of_copy"] = achieved / ceil
+    out["roofline"]["frac_of_copy"] = r["achieved"] / ceil
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["accuracy"] = cpu_baseline(w, T0_host, b_host, dt, precision, torch, rkl)
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        out["cpu_baseline"], out["accuracy"] = horizon_check(w, precision, torch, rkl, threads)
+        out["accuracy"]["per_config_from_tests"] = horizon_errors_from_tests()
     print(json.dumps(out), flush=True)
 
 

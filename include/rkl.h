@@ -71,7 +71,8 @@ enum { RKL_BC_PERIODIC = 0, RKL_BC_OUTFLOW = 1 };
 enum {
     RKL_FLAG_NONPOS = 1u,     /* some input temperature <= 0 (conductivity clipped at 0) */
     RKL_FLAG_NONFINITE = 2u,  /* some input temperature is NaN or infinite */
-    RKL_FLAG_STAGES = 4u      /* the stage count exceeded smax; that grid was not advanced */
+    RKL_FLAG_STAGES = 4u,     /* the stage count exceeded smax; that grid was not advanced */
+    RKL_FLAG_ABORTED = 8u     /* the last persistent batched launch gave up a wait (results invalid) */
 };
 
 /* One grid and its conduction parameters. */
@@ -274,7 +275,8 @@ rkl_status rkl_set_variant(rkl_plan_t plan, int32_t variant);
  * launch of rkl_subcycle and rkl_aag; rkl_profile(plan, 0) stops and
  * discards.
  * rkl_profile_read synchronises and returns, over the launches of one kind
- * -- `fuse` 1: one-stage, 2: two-stage, 3: forward-Euler sub-steps -- the summed
+ * -- `fuse` 1: one-stage, 2: two-stage, 3: forward-Euler sub-steps, 4: the
+ * persistent batched launch (all stages of a super-step) -- the summed
  * duration in ms, the number of launches and of cell updates (batched
  * launches count 0: their work follows from the device-side stage counts).
  */
@@ -303,9 +305,28 @@ rkl_status rkl_autotune(rkl_plan_t plan, int32_t grid, const double *T, const vo
  * the next capture).  rkl_autotune_batched times `reps` batched super-steps
  * with every policy on a plan-owned scratch copy of the packed T (T itself
  * is not modified; dt_hyp is the device array of ngrids doubles), selects
- * the fastest and returns its index and average super-step time.  It
+ * the fastest and returns its index and average super-step time (both
+ * launch modes, see rkl_set_batch_mode).  It
  * allocates the scratch for the duration of the call and synchronises.
  */
+/*
+ * rkl_set_batch_mode: how rkl_superstep_batched (and a graph captured from
+ * it) launches a super-step.  mode 0 (default): one reduce launch, then one
+ * launch per stage j = 1..smax over every tile of every grid.  mode 1: three
+ * launches -- the reduce launch, a schedule launch that lists the work items
+ * (stage j, grid, tile) stage after stage for the grids' device-side stage
+ * counts, and one persistent launch whose workgroups take the items in list
+ * order from an atomic counter; an item of stage j of a grid waits (on the
+ * device) until every tile of stages 1..j-1 of that grid is done.  An item
+ * only ever waits for items earlier in the list, all of them taken by running
+ * workgroups, so the launch needs no co-residency guarantee; every wait is
+ * bounded (2 s), and a launch that gives up sets RKL_FLAG_ABORTED (rkl_query)
+ * and leaves the results invalid.  Same bits as mode 0.  mode 1 needs smax <=
+ * 256 and allocates the item list (16 B x tiles x smax) on first use.  A
+ * captured graph is dropped.  rkl_autotune_batched times both modes; the
+ * index it returns is policy + mode x rkl_batch_policy_count().
+ */
+rkl_status rkl_set_batch_mode(rkl_plan_t plan, int32_t mode);
 int32_t rkl_batch_policy_count(void);
 rkl_status rkl_batch_policy_info(int32_t policy, int32_t *half_rows, int32_t *tile_z);
 rkl_status rkl_set_batch_policy(rkl_plan_t plan, int32_t policy);

@@ -53,6 +53,7 @@ struct rkl_plan_s {
     int32_t* s_host = nullptr;  // pinned
     BatchPlan* batch = nullptr; // batched launch data (rkl_batch.hip)
     int batch_policy = 0;       // its tile policy
+    int batch_mode = 0;         // 0: one launch per stage; 1: one persistent launch
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     // kernel timing (rkl_profile): one event pair per stencil launch of
@@ -178,12 +179,19 @@ static void free_plan(rkl_plan_s* p) {
 }
 
 static rkl_status ensure_batch(rkl_plan_s* p) {
-    if (p->batch) return RKL_OK;
-    // the batched stage routing writes stage j = s into T, which needs s >= 2
-    if (p->scheme != RKL_RKL2) return fail(RKL_EINVAL, "the batched super-step implements RKL2 only");
-    std::string why;
-    rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, p->batch_policy, &p->batch, why);
-    return st == RKL_OK ? RKL_OK : fail(st, why);
+    if (!p->batch) {
+        // the batched stage routing writes stage j = s into T, which needs s >= 2
+        if (p->scheme != RKL_RKL2) return fail(RKL_EINVAL, "the batched super-step implements RKL2 only");
+        std::string why;
+        rkl_status st = batch_create(p->desc, p->gc, p->off, p->precision, p->smax, p->batch_policy, &p->batch, why);
+        if (st != RKL_OK) return fail(st, why);
+    }
+    if (p->batch_mode == 1) {
+        std::string why;
+        rkl_status st = batch_persist_init(p->batch, why);
+        if (st != RKL_OK) return fail(st, why);
+    }
+    return RKL_OK;
 }
 
 // A plan's buffers live on the device that was current at rkl_plan; its
@@ -199,18 +207,36 @@ static rkl_status check_plan(const rkl_plan_s* p) {
     return RKL_OK;
 }
 
+static void drop_graph(rkl_plan_s* p) {
+    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+}
+
 // Replace the batched launch data by that of `policy`; a captured graph
 // refers to the old data, so it is dropped.
 static rkl_status select_batch_policy(rkl_plan_s* p, int policy) {
     if (p->batch && policy == p->batch_policy) return RKL_OK;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hipfail(e, "policy sync");
-    if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
-    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    drop_graph(p);
     batch_free(p->batch);
     p->batch = nullptr;
     p->batch_policy = policy;
     return ensure_batch(p);
+}
+
+// Select the batched launch mode; a captured graph holds the old launch
+// sequence, so it is dropped.
+static rkl_status select_batch_mode(rkl_plan_s* p, int mode) {
+    if (mode == p->batch_mode) return ensure_batch(p);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hipfail(e, "mode sync");
+    drop_graph(p);
+    const int old = p->batch_mode;
+    p->batch_mode = mode;
+    rkl_status st = ensure_batch(p);
+    if (st != RKL_OK) p->batch_mode = old;
+    return st;
 }
 
 extern "C" {
@@ -226,6 +252,12 @@ rkl_status rkl_batch_policy_info(int32_t policy, int32_t* half_rows, int32_t* ti
     if (half_rows) *half_rows = h;
     if (tile_z) *tile_z = z;
     return RKL_OK;
+}
+
+rkl_status rkl_set_batch_mode(rkl_plan_t p, int32_t mode) {
+    if (rkl_status st = check_plan(p)) return st;
+    if (mode != 0 && mode != 1) return fail(RKL_EINVAL, "batch mode must be 0 (per-stage launches) or 1 (persistent)");
+    return select_batch_mode(p, mode);
 }
 
 rkl_status rkl_set_batch_policy(rkl_plan_t p, int32_t policy) {
@@ -246,41 +278,52 @@ rkl_status rkl_autotune_batched(rkl_plan_t p, const double* T, const void* b, co
     HIPCHECK(hipMalloc(&W, bytes), "autotune scratch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const bool saved_prof = p->prof;
-    const int saved = p->batch_policy;
+    const int saved = p->batch_policy, saved_mode = p->batch_mode;
     p->prof = false;
-    int best = -1;
+    int best = -1, best_mode = 0;
     float best_t = 0.f;
     rkl_status res = RKL_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) res = fail(RKL_EDEVICE, "autotune events");
-    for (int pol = 0; res == RKL_OK && pol < batch_policy_count(); ++pol) {
-        res = select_batch_policy(p, pol);
-        if (res != RKL_OK) break;
-        BatchBuffers bb{W, b, dt_hyp, nullptr, p->Ya, p->Yb, p->MY0, p->coef, p->state};
-        // one untimed super-step from the caller's T, then reps timed ones
-        hipError_t e = hipMemcpyAsync(W, T, bytes, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = batch_launch(p->batch, bb, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(W, T, bytes, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int r = 0; e == hipSuccess && r < reps; ++r) e = batch_launch(p->batch, bb, s);
-        float t = 0.f;
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-        if (e != hipSuccess) { res = hipfail(e, "batched autotune"); break; }
-        if (best < 0 || t < best_t) { best = pol; best_t = t; }
+    // every tile policy with per-stage launches, then with the persistent launch
+    // (if the plan's smax allows it)
+    for (int mode = 0; res == RKL_OK && mode < 2; ++mode) {
+        if (mode == 1 && p->smax > 256) break;
+        for (int pol = 0; res == RKL_OK && pol < batch_policy_count(); ++pol) {
+            res = select_batch_policy(p, pol);
+            if (res == RKL_OK) res = select_batch_mode(p, mode);
+            if (res != RKL_OK) break;
+            BatchBuffers bb{W, b, dt_hyp, nullptr, p->Ya, p->Yb, p->MY0, p->coef, p->state};
+            // one untimed super-step from the caller's T, then reps timed ones
+            hipError_t e = hipMemcpyAsync(W, T, bytes, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = batch_launch(p->batch, bb, s, nullptr, mode);
+            if (e == hipSuccess) e = hipMemcpyAsync(W, T, bytes, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int r = 0; e == hipSuccess && r < reps; ++r) e = batch_launch(p->batch, bb, s, nullptr, mode);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) { res = hipfail(e, "batched autotune"); break; }
+            bool aborted = false;
+            if (mode == 1 && (e = batch_aborted(p->batch, &aborted)) != hipSuccess) { res = hipfail(e, "abort word"); break; }
+            if (aborted) continue;   // a persistent launch that gave up is never chosen
+            if (best < 0 || t < best_t) { best = pol; best_mode = mode; best_t = t; }
+        }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s);
     (void)hipFree(W);
     p->prof = saved_prof;
-    if (res != RKL_OK) {
+    if (res != RKL_OK || best < 0) {
         select_batch_policy(p, saved);
-        return res;
+        select_batch_mode(p, saved_mode);
+        return res != RKL_OK ? res : fail(RKL_EDEVICE, "batched autotune: no configuration completed");
     }
     res = select_batch_policy(p, best);
+    if (res == RKL_OK) res = select_batch_mode(p, best_mode);
     if (res != RKL_OK) return res;
-    if (best_policy) *best_policy = best;
+    if (best_policy) *best_policy = best + best_mode * batch_policy_count();
     if (best_ms) *best_ms = best_t / reps;
     return RKL_OK;
 }
@@ -304,6 +347,10 @@ static bool fused_ok(const rkl_plan_s* p) {
     for (const auto& d : p->desc)
         if (d.ndim != 3 || d.boundary[0] || d.boundary[1] || d.boundary[2]) return false;
     return true;
+}
+
+static bool variant_ok(const rkl_plan_s* p, const Variant& x) {
+    return x.fuse == 2 ? fused_ok(p) : true;
 }
 
 static rkl_status select_variant(rkl_plan_s* p, int v) {
@@ -713,7 +760,7 @@ rkl_status rkl_autotune(rkl_plan_t p, int32_t g, const double* T, const void* b,
         res = fail(RKL_EDEVICE, "autotune events");
     }
     for (int v = 0; res == RKL_OK && v < variant_count(); ++v) {
-        if (variant_get(v).fuse == 2 && !fused_ok(p)) continue;
+        if (!variant_ok(p, variant_get(v))) continue;
         res = select_variant(p, v);
         if (res != RKL_OK) break;
         // one untimed super-step from the caller's T, then reps timed ones
@@ -754,7 +801,7 @@ rkl_status rkl_profile(rkl_plan_t p, int32_t enable) {
 
 rkl_status rkl_profile_read(rkl_plan_t p, int32_t fuse, double* ms, int64_t* launches, int64_t* cells) {
     if (rkl_status st = check_plan(p)) return st;
-    if (fuse < 1 || fuse > 3) return fail(RKL_EINVAL, "fuse must be 1, 2 or 3");
+    if (fuse < 1 || fuse > 4) return fail(RKL_EINVAL, "fuse must be 1, 2, 3 or 4");
     double tot = 0.0;
     int64_t nl = 0, nc = 0;
     for (const auto& r : p->prof_recs) {
@@ -778,9 +825,11 @@ rkl_status rkl_query(rkl_plan_t p, int32_t g, int32_t* last_s, double* last_dt_p
     GridState h;
     HIPCHECK(hipDeviceSynchronize(), "query sync");
     HIPCHECK(hipMemcpy(&h, p->state + g, sizeof h, hipMemcpyDeviceToHost), "query copy");
+    bool aborted = false;
+    if (p->batch_mode == 1) HIPCHECK(batch_aborted(p->batch, &aborted), "abort word");
     if (last_s) *last_s = h.s;
     if (last_dt_par) *last_dt_par = h.dt_par;
-    if (flags) *flags = h.flags;
+    if (flags) *flags = h.flags | (aborted ? (uint32_t)RKL_FLAG_ABORTED : 0u);
     return RKL_OK;
 }
 
@@ -793,10 +842,11 @@ rkl_status rkl_superstep_batched(rkl_plan_t p, double* T, const void* b, const d
     if (st != RKL_OK) return st;
     BatchBuffers bb{T, b, dt_hyp, s_out, p->Ya, p->Yb, p->MY0, p->coef, p->state};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-    hipError_t e = batch_launch(p->batch, bb, (hipStream_t)stream, p->prof ? &ev : nullptr);
+    hipError_t e = batch_launch(p->batch, bb, (hipStream_t)stream, p->prof ? &ev : nullptr, p->batch_mode);
     // cell-stages of a batched launch depend on the device-side stage counts:
-    // recorded as 0 (the caller knows them from s_out)
-    for (auto& x : ev) p->prof_recs.push_back({x.first, x.second, 1, 0});
+    // recorded as 0 (the caller knows them from s_out); the persistent launch
+    // is recorded as kind 4
+    for (auto& x : ev) p->prof_recs.push_back({x.first, x.second, p->batch_mode == 1 ? 4 : 1, 0});
     if (e != hipSuccess) return hipfail(e, "batched launch");
     return RKL_OK;
 }
@@ -814,7 +864,7 @@ rkl_status rkl_graph_capture(rkl_plan_t p, double* T, const void* b, const doubl
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { (void)hipStreamDestroy(cap); return hipfail(e, "begin capture"); }
     BatchBuffers bb{T, b, dt_hyp, s_out, p->Ya, p->Yb, p->MY0, p->coef, p->state};
-    hipError_t le = batch_launch(p->batch, bb, cap);
+    hipError_t le = batch_launch(p->batch, bb, cap, nullptr, p->batch_mode);
     hipGraph_t gr = nullptr;
     e = hipStreamEndCapture(cap, &gr);
     (void)hipStreamDestroy(cap);

@@ -30,10 +30,16 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
 int batch_policy_count();
 void batch_policy_info(int policy, int* half_rows, int* bz);
 void batch_free(BatchPlan* bp);
-// Enqueue one super-step of every grid (no host synchronisation).  With
-// `events` non-NULL, a pair of HIP events (created here, owned by the caller)
-// is recorded around each launch of stages j >= 2.
+// Enqueue one super-step of every grid (no host synchronisation).  mode 0:
+// one launch per stage; mode 1: the persistent launch (batch_persist_init
+// first).  With `events` non-NULL, a pair of HIP events (created here, owned
+// by the caller) is recorded around each launch of stages j >= 2 (mode 0) or
+// around the persistent launch (mode 1).
 hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st,
-                        std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr);
+                        std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr, int mode = 0);
+// Buffers and launch size of the persistent mode (once per plan).
+rkl_status batch_persist_init(BatchPlan* bp, std::string& why);
+// Whether the last persistent launch gave up a wait (synchronous read).
+hipError_t batch_aborted(const BatchPlan* bp, bool* aborted);
 
 }  // namespace rkl

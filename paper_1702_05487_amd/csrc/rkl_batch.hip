@@ -11,10 +11,29 @@
 // are dispatched largest grid first so that the small tiles fill the tail of
 // each launch.
 //
+// Persistent mode (rkl_set_batch_mode): three launches per super-step.  The
+// reduce launch as above (it also clears each grid's completed-tile
+// counter); a schedule launch (one workgroup) that lays out the work items
+// -- (stage j, grid, tile) for every tile of every grid whose s reaches j,
+// stage-major, so stage j of every grid comes after stage j-1 of every grid
+// -- and clears the ticket counter; and one persistent launch whose
+// workgroups take items in list order from an atomic ticket counter.  An item of stage j >= 2 of grid g first waits
+// until all (j-1) x ntiles(g) tiles of stages 1..j-1 of g are complete
+// (g's completed-tile counter, released at agent scope after each tile and
+// acquired before the wait ends), then runs the tile and counts it.
+// No wait depends on a workgroup that has not started: an item waits only
+// for items earlier in the list, and items are handed out in list order, so
+// the earliest unfinished item has every item it waits for finished and its
+// workgroup (which took it, so is running) proceeds; no assumption about how
+// many workgroups are resident at once is needed.  Every wait is bounded:
+// after `timeout` wall-clock ticks a waiting workgroup sets the abort word and
+// exits, every other workgroup exits at its next item or poll, and the plan
+// reports RKL_FLAG_ABORTED.
+//
 // Tile shapes are chosen per grid by a tile policy (z-chunk length; full- or
 // half-width rows, so that a patch narrower than 64 cells has no ragged x
 // tiles); every tile runs the same run_tile code as the single-grid kernels,
-// so the policy never changes the result.
+// so neither the policy nor the mode changes the result.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -47,19 +66,42 @@ struct BatchGrid {
     int ntiles;
 };
 
+// control words of the persistent launch (device)
+struct PersistCtl {
+    unsigned long long ticket;   // next item to hand out
+    unsigned long long total;    // items of this super-step (schedule launch)
+    unsigned int abort;          // set by a workgroup whose wait gave up
+    unsigned int pad;
+};
+
+constexpr int kPersistSmax = 256;   // stage counts the persistent schedule handles
+
 struct BatchPlan {
     int ngrids = 0, precision = 0, smax = 0, items = 0;
     int limiter = 0, saturation = 0, kmode = 0;
     BatchGrid* grids = nullptr;   // device
     int2* items_dev = nullptr;    // device, item -> (grid, tile), largest grids first
+    // persistent mode (allocated on first use)
+    int* by_size = nullptr;       // device, grid ids, largest grid first
+    int* order = nullptr;         // device, grids by stage count (schedule launch)
+    int* tprefix = nullptr;       // device, ngrids + 1 tile prefix sums over `order`
+    int2* tiles = nullptr;        // device, items: (grid, tile) in `order`
+    unsigned long long* base = nullptr;   // device, smax + 2: first ticket of stage j
+    PersistCtl* ctl = nullptr;    // device
+    unsigned int* done = nullptr; // device, ngrids completed-tile counters
+    int persist_blocks = 0;       // workgroups of the persistent launch
+    long long timeout = 0;        // wall-clock ticks a wait may last
+    std::vector<int> by_size_host;
 };
 
 // one workgroup per grid: extrema of T, then dt_par and s for that grid
 __global__ __launch_bounds__(kBT) void batch_reduce_kernel(const BatchGrid* __restrict__ grids,
                                                            const double* __restrict__ T,
                                                            const double* __restrict__ dt_hyp,
-                                                           GridState* state, int32_t* s_out, int smax) {
+                                                           GridState* state, int32_t* s_out, int smax,
+                                                           unsigned int* done) {
     const int g = blockIdx.x;
+    if (done && threadIdx.x == 0) done[g] = 0u;
     const BatchGrid G = grids[g];
     const int64_t N = (int64_t)G.gc.n0 * G.gc.n1 * G.gc.n2;
     const double* t = T + G.off;
@@ -172,6 +214,118 @@ __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int
     batch_tile<R, LIM, SAT, KM>(P, it.x, stage, it.y, st, L);
 }
 
+// Schedule of the persistent launch (one workgroup).  Thread 0 orders the
+// grids by stage count, largest first (stable over the largest-grid-first
+// order), counts for every stage j the grids that reach it, cnt(j), and lays
+// the stages out one after another: stage j's items are the tiles of the
+// first cnt(j) grids of that order, i.e. a prefix of one list of all tiles in
+// that order, and start at ticket base[j].  Grids flagged at the reduce step
+// (s above smax, or a bad dt_hyp) have no items.  The workgroup then writes
+// the tile list.
+__global__ __launch_bounds__(kBT) void batch_schedule_kernel(const BatchGrid* __restrict__ grids,
+                                                             const int* __restrict__ by_size,
+                                                             const GridState* __restrict__ state, int ngrids,
+                                                             int smax, int* order, int* tprefix, int2* tiles,
+                                                             unsigned long long* base, PersistCtl* ctl) {
+    __shared__ int cnt[kPersistSmax + 2];        // cnt[j]: grids with s >= j
+    __shared__ int pos[kPersistSmax + 2];
+    if (threadIdx.x == 0) {
+        for (int j = 0; j <= smax + 1; ++j) { cnt[j] = 0; pos[j] = 0; }
+        for (int g = 0; g < ngrids; ++g) {
+            const GridState& st = state[g];
+            const int se = (st.flags & RKL_FLAG_STAGES) || st.s < 2 || st.s > smax ? 0 : st.s;
+            cnt[se] += 1;                          // histogram of the stage counts
+        }
+        // first position of each stage count in the order (larger s first)
+        int acc = 0;
+        for (int v = smax; v >= 0; --v) { pos[v] = acc; acc += cnt[v]; }
+        for (int k = 0; k < ngrids; ++k) {
+            const int g = by_size[k];
+            const GridState& st = state[g];
+            const int se = (st.flags & RKL_FLAG_STAGES) || st.s < 2 || st.s > smax ? 0 : st.s;
+            order[pos[se]++] = g;
+        }
+        int ge = 0;
+        for (int v = smax; v >= 1; --v) { ge += cnt[v]; cnt[v] = ge; }   // grids with s >= v
+        int tp = 0;
+        for (int i = 0; i < ngrids; ++i) { tprefix[i] = tp; tp += grids[order[i]].ntiles; }
+        tprefix[ngrids] = tp;
+        unsigned long long b = 0;
+        for (int j = 1; j <= smax; ++j) { base[j] = b; b += (unsigned long long)tprefix[cnt[j]]; }
+        base[0] = 0;
+        base[smax + 1] = b;
+        ctl->ticket = 0ull;
+        ctl->total = b;
+        ctl->abort = 0u;
+    }
+    __syncthreads();
+    for (int i = 0; i < cnt[1]; ++i) {
+        const int g = order[i], nt = grids[g].ntiles;
+        int2* w = tiles + tprefix[i];
+        for (int t = threadIdx.x; t < nt; t += kBT) w[t] = make_int2(g, t);
+    }
+}
+
+template <typename R, bool LIM, int SAT, int KM>
+__global__ __launch_bounds__(kBT) void batch_persistent_kernel(BatchBufs P, const int2* __restrict__ tiles,
+                                                               const unsigned long long* __restrict__ base,
+                                                               int smax, PersistCtl* ctl, unsigned int* done,
+                                                               long long timeout) {
+    __shared__ TileLds<R, Cap<R>::PL, Cap<R>::FX, Cap<R>::FY> L;
+    __shared__ unsigned long long sbase[kPersistSmax + 2];
+    __shared__ int3 item;   // (stage, grid, tile)
+    __shared__ int ok;
+    for (int j = threadIdx.x; j <= smax + 1; j += kBT) sbase[j] = base[j];
+    const unsigned long long total = ctl->total;
+    int j = 1;   // stage of the last ticket (tickets only grow)
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int go = 0;
+            int3 it = make_int3(0, 0, 0);
+            if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+                const unsigned long long t =
+                    __hip_atomic_fetch_add(&ctl->ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (t < total) {
+                    while (t >= sbase[j + 1]) ++j;
+                    const int2 gt = tiles[t - sbase[j]];
+                    it = make_int3(j, gt.x, gt.y);
+                    go = 1;
+                    if (j >= 2) {
+                        // stages 1..j-1 of this grid complete: (j-1) x ntiles tiles counted
+                        const unsigned int need = (unsigned int)(j - 1) * (unsigned int)P.grids[gt.x].ntiles;
+                        const long long t0 = wall_clock64();
+                        while (__hip_atomic_load(&done[gt.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                            if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                                go = 0;
+                                break;
+                            }
+                            if (wall_clock64() - t0 > timeout) {
+                                __hip_atomic_store(&ctl->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                go = 0;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(8);
+                        }
+                        // the other workgroups' stage outputs are visible from here on
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                }
+            }
+            item = it;
+            ok = go;
+        }
+        __syncthreads();
+        if (!ok) break;   // uniform over the workgroup
+        const int3 it = item;
+        const GridState st = P.state[it.y];
+        batch_tile<R, LIM, SAT, KM>(P, it.y, it.x, it.z, st, L);
+        __syncthreads();
+        // every store of the tile is done; publish it with the count
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[it.y], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // Tile policies of the batched launch: z-chunk length and row width.  Rows
 // are the grid's full width (up to 64 cells), or half of it for grids wider
 // than 32 cells (twice the tiles, shorter halo rows); by fills the 256
@@ -249,6 +403,7 @@ rkl_status batch_create(const std::vector<rkl_grid_desc>& desc, const std::vecto
         for (int t = 0; t < h[g].ntiles; ++t) item_list.push_back(make_int2(g, t));
 
     BatchPlan* bp = new BatchPlan();
+    bp->by_size_host = by_size;
     bp->ngrids = n;
     bp->precision = precision;
     bp->smax = smax;
@@ -279,7 +434,103 @@ void batch_free(BatchPlan* bp) {
     if (!bp) return;
     (void)hipFree(bp->grids);
     (void)hipFree(bp->items_dev);
+    (void)hipFree(bp->by_size);
+    (void)hipFree(bp->order);
+    (void)hipFree(bp->tprefix);
+    (void)hipFree(bp->tiles);
+    (void)hipFree(bp->base);
+    (void)hipFree(bp->ctl);
+    (void)hipFree(bp->done);
     delete bp;
+}
+
+template <typename R, bool LIM, int KM>
+static const void* persistent_fn(int sat) {
+    if (sat == 2) return (const void*)batch_persistent_kernel<R, LIM, 2, KM>;
+    if (sat == 1) return (const void*)batch_persistent_kernel<R, LIM, 1, KM>;
+    return (const void*)batch_persistent_kernel<R, LIM, 0, KM>;
+}
+
+template <typename R>
+static const void* persistent_fn(const BatchPlan* bp) {
+    const bool lim = bp->limiter != 0;
+    if (bp->kmode == 0) return lim ? persistent_fn<R, true, 0>(bp->saturation) : persistent_fn<R, false, 0>(bp->saturation);
+    if (bp->kmode == 1) return lim ? persistent_fn<R, true, 1>(bp->saturation) : persistent_fn<R, false, 1>(bp->saturation);
+    return lim ? persistent_fn<R, true, 2>(bp->saturation) : persistent_fn<R, false, 2>(bp->saturation);
+}
+
+rkl_status batch_persist_init(BatchPlan* bp, std::string& why) {
+    if (bp->ctl) return RKL_OK;
+    if (bp->smax > kPersistSmax) {
+        why = "the persistent batched launch needs smax <= " + std::to_string(kPersistSmax);
+        return RKL_EINVAL;
+    }
+    const int n = bp->ngrids;
+    bool ok = hipMalloc(&bp->by_size, sizeof(int) * n) == hipSuccess &&
+              hipMalloc(&bp->order, sizeof(int) * n) == hipSuccess &&
+              hipMalloc(&bp->tprefix, sizeof(int) * (n + 1)) == hipSuccess &&
+              hipMalloc(&bp->tiles, sizeof(int2) * (size_t)bp->items) == hipSuccess &&
+              hipMalloc(&bp->base, sizeof(unsigned long long) * (kPersistSmax + 2)) == hipSuccess &&
+              hipMalloc(&bp->ctl, sizeof(PersistCtl)) == hipSuccess &&
+              hipMalloc(&bp->done, sizeof(unsigned int) * n) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        why = "device allocation failed (persistent batched launch)";
+        return RKL_ENOMEM;
+    }
+    const PersistCtl zero{0ull, 0ull, 0u, 0u};
+    int dev = 0, cus = 0, per_cu = 0, rate_khz = 0;
+    hipError_t e = hipMemcpy(bp->by_size, bp->by_size_host.data(), sizeof(int) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bp->ctl, &zero, sizeof zero, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, bp->precision == RKL_MIXED ? persistent_fn<float>(bp) : persistent_fn<double>(bp), kBT, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        why = std::string("persistent launch set-up: ") + hipGetErrorString(e);
+        return RKL_EDEVICE;
+    }
+    bp->persist_blocks = std::max(1, per_cu) * std::max(1, cus);
+    // a wait longer than 2 s means something is wrong: give up (a whole
+    // super-step of the largest workloads takes a few tens of milliseconds)
+    if (rate_khz <= 0) rate_khz = 100000;   // the usual 100 MHz counter
+    bp->timeout = (long long)rate_khz * 2000ll;
+    return RKL_OK;
+}
+
+hipError_t batch_aborted(const BatchPlan* bp, bool* aborted) {
+    *aborted = false;
+    if (!bp || !bp->ctl) return hipSuccess;
+    PersistCtl h;
+    hipError_t e = hipMemcpy(&h, bp->ctl, sizeof h, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) *aborted = h.abort != 0u;
+    return e;
+}
+
+template <typename R, bool LIM, int KM>
+static void launch_persist_sat(const BatchPlan* bp, const BatchBufs& a, hipStream_t st) {
+    const int nb = bp->persist_blocks;
+    if (bp->saturation == 2)
+        batch_persistent_kernel<R, LIM, 2, KM><<<nb, kBT, 0, st>>>(a, bp->tiles, bp->base, bp->smax, bp->ctl,
+                                                                   bp->done, bp->timeout);
+    else if (bp->saturation == 1)
+        batch_persistent_kernel<R, LIM, 1, KM><<<nb, kBT, 0, st>>>(a, bp->tiles, bp->base, bp->smax, bp->ctl,
+                                                                   bp->done, bp->timeout);
+    else
+        batch_persistent_kernel<R, LIM, 0, KM><<<nb, kBT, 0, st>>>(a, bp->tiles, bp->base, bp->smax, bp->ctl,
+                                                                   bp->done, bp->timeout);
+}
+
+template <typename R>
+static void launch_persist(const BatchPlan* bp, const BatchBufs& a, hipStream_t st) {
+    const bool lim = bp->limiter != 0;
+    if (bp->kmode == 0) { if (lim) launch_persist_sat<R, true, 0>(bp, a, st); else launch_persist_sat<R, false, 0>(bp, a, st); }
+    else if (bp->kmode == 1) { if (lim) launch_persist_sat<R, true, 1>(bp, a, st); else launch_persist_sat<R, false, 1>(bp, a, st); }
+    else { if (lim) launch_persist_sat<R, true, 2>(bp, a, st); else launch_persist_sat<R, false, 2>(bp, a, st); }
 }
 
 template <typename R, bool LIM, int KM>
@@ -304,9 +555,11 @@ static void launch_stage_b(const BatchPlan* bp, const BatchBufs& a, int stage, h
 }
 
 hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st,
-                        std::vector<std::pair<hipEvent_t, hipEvent_t>>* events) {
+                        std::vector<std::pair<hipEvent_t, hipEvent_t>>* events, int mode) {
+    const bool persist = mode == 1;
+    if (persist && !bp->ctl) return hipErrorNotInitialized;
     batch_reduce_kernel<<<bp->ngrids, kBT, 0, st>>>(bp->grids, buf.T, buf.dt_hyp, buf.state, buf.s_out,
-                                                    bp->smax);
+                                                    bp->smax, persist ? bp->done : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     BatchBufs a;
@@ -318,6 +571,23 @@ hipError_t batch_launch(BatchPlan* bp, const BatchBuffers& buf, hipStream_t st,
     a.Ya = buf.Ya;
     a.Yb = buf.Yb;
     a.MY0 = buf.MY0;
+    if (persist) {
+        batch_schedule_kernel<<<1, kBT, 0, st>>>(bp->grids, bp->by_size, buf.state, bp->ngrids, bp->smax, bp->order,
+                                                 bp->tprefix, bp->tiles, bp->base, bp->ctl);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (events) {
+            if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+            if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return e; }
+            events->push_back({e0, e1});
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) return e;
+        }
+        if (bp->precision == RKL_MIXED) launch_persist<float>(bp, a, st);
+        else launch_persist<double>(bp, a, st);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (e1 && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
+        return hipSuccess;
+    }
     for (int j = 1; j <= bp->smax; ++j) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (events && j >= 2) {

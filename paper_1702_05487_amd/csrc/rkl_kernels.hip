@@ -3,9 +3,7 @@
 // dt_par, the stage count s and the stage scale (Sec. 3.1 Eq. dt_exp,
 // Sec. 3.3 Eq. RKL-s, Sec. 4.1 rounding), and the stencil/stage kernels that
 // wrap run_tile (rkl_tile.h).
-#include "rkl_internal.h"
-#include "rkl_tile.h"
-#include "../../include/rkl.h"
+#include "rkl_stage.h"
 
 namespace rkl {
 
@@ -104,101 +102,10 @@ hipError_t launch_finalize(const double* partials, int nblocks, const GridConst&
 }
 
 // -------------------------------------------------------- stage kernels ----
-struct StageLaunch {
-    TileArgs t;          // everything but the tile origin, z range and coefficients
-    int ntx, nty, bz;
-    const GridState* state;
-    const double* coef;  // RKL2 table: 5 doubles per (s, j), row of s at s(s+1)/2
-    int stage;
-    double kappa0, kexp, kperp, satq;
-    int kmode;
-    double fac;
-    double sub_scale;    // kind 3: -tau_sub (gamma-1)/rho
-    Route route;         // route.A != NULL: Yin, Ym2, Yout chosen on the device (kinds 1, 2)
-};
-
-// FIX3: 3-D grid, tile shape fixed at compile time (run_tile's CBX, CBY)
-template <typename R, bool LIM, int SAT, int KM, int BX, int BY, bool FIX3>
-__global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
-    constexpr int PL = (BX + 2) * (BY + 2);
-    __shared__ TileLds<R, PL, (BX + 1) * BY, BX*(BY + 1)> L;
-    int bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int tile_x = bid % P.ntx;
-    bid /= P.ntx;
-    const int tile_y = bid % P.nty;
-    const int zc = bid / P.nty;
-
-    TileArgs a = P.t;
-    a.bx = BX;
-    a.by = BY;
-    a.x0 = tile_x * BX;
-    a.y0 = tile_y * BY;
-    a.z0 = zc * P.bz;
-    a.z1 = min(a.z0 + P.bz, a.n2);
-
-    const GridState* st = P.state;
-    double tref = 0.0;
-    if (sizeof(R) == 4) tref = st->tref;
-    if (a.kind == 0) {
-        a.scale = -P.fac;
-    } else if (a.kind == 3) {
-        a.scale = P.sub_scale;
-    } else {
-        const int s = st->s;
-        if (P.route.A) {
-            // the stage sequence was launched up to s_cap without knowing s
-            if (P.stage > s || s < 2 || s > P.route.s_cap) return;   // uniform over the grid
-            const int j = P.stage;
-            double* T = a.Yout;   // the caller's T (Y_0, and Y_s)
-            double* Yj = (j & 1) ? P.route.A : P.route.B;
-            if (j == 1) {
-                a.Yin = T;
-            } else {
-                a.Yin = ((j - 1) & 1) ? P.route.A : P.route.B;
-                a.Ym2 = j == 2 ? T : Yj;   // Y_{j-2} sits where Y_j goes
-            }
-            a.Yout = j == s ? T : Yj;
-        }
-        const double* cf = P.coef + 5 * (P.route.coef_flat ? (size_t)P.stage : (size_t)s * (s + 1) / 2 + P.stage);
-        a.mu = cf[0];
-        a.nu = cf[1];
-        a.omn = cf[2];
-        a.mut = cf[3];
-        a.gt = cf[4];
-        a.scale = -st->cdiv;
-    }
-    const FaceK<R> fk = make_facek<R>(P.kappa0, P.kexp, P.kperp, P.satq, tref);
-    if constexpr (FIX3)
-        run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), BX, BY>(a, fk, tref, L);
-    else
-        run_tile<R, LIM, SAT, KM>(a, fk, tref, L);
-}
-
-template <typename R, bool LIM, int KM, int BX, int BY, bool FIX3>
-static void launch_sat(const StageLaunch& P, int nblocks, int sat, hipStream_t st) {
-    if (sat == 2) stage_kernel<R, LIM, 2, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (sat == 1) stage_kernel<R, LIM, 1, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
-    else stage_kernel<R, LIM, 0, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
-}
-
-template <typename R, int KM, int BX, int BY, bool FIX3>
-static void launch_fix(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
-    if (lim) launch_sat<R, true, KM, BX, BY, FIX3>(P, nblocks, sat, st);
-    else launch_sat<R, false, KM, BX, BY, FIX3>(P, nblocks, sat, st);
-}
-
-template <typename R, int KM, int BX, int BY>
-static void launch_km(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
-    if (P.t.ndim == 3) launch_fix<R, KM, BX, BY, true>(P, nblocks, lim, sat, st);
-    else launch_fix<R, KM, BX, BY, false>(P, nblocks, lim, sat, st);
-}
-
 template <typename R, int BX, int BY>
 static hipError_t launch_shape(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
-    if (P.kmode == 0) launch_km<R, 0, BX, BY>(P, nblocks, lim, sat, st);
-    else if (P.kmode == 1) launch_km<R, 1, BX, BY>(P, nblocks, lim, sat, st);
-    else launch_km<R, 2, BX, BY>(P, nblocks, lim, sat, st);
-    return hipGetLastError();
+    if (P.t.ndim == 3) return launch_law<R, BX, BY, true>(P, nblocks, lim, sat, st);
+    return launch_law<R, BX, BY, false>(P, nblocks, lim, sat, st);
 }
 
 template <typename R>

@@ -21,7 +21,7 @@ RKL_LIM_NONE, RKL_LIM_MC = 0, 1
 RKL_SAT_NONE, RKL_SAT_CENTRAL, RKL_SAT_UPWIND = 0, 1, 2
 RKL_BC_PERIODIC, RKL_BC_OUTFLOW = 0, 1
 RKL_RKL2, RKL_RKL1 = 0, 1
-RKL_FLAG_NONPOS, RKL_FLAG_NONFINITE, RKL_FLAG_STAGES = 1, 2, 4
+RKL_FLAG_NONPOS, RKL_FLAG_NONFINITE, RKL_FLAG_STAGES, RKL_FLAG_ABORTED = 1, 2, 4, 8
 
 EXPORTS = [
     "rkl_plan", "rkl_destroy", "rkl_grid_offset", "rkl_flux_div", "rkl_dt_par",
@@ -29,6 +29,7 @@ EXPORTS = [
     "rkl_query", "rkl_variant_count", "rkl_variant_info", "rkl_set_variant", "rkl_last_error",
     "rkl_profile", "rkl_profile_read", "rkl_autotune",
     "rkl_batch_policy_count", "rkl_batch_policy_info", "rkl_set_batch_policy", "rkl_autotune_batched",
+    "rkl_set_batch_mode",
     "rkl_subcycle", "rkl_aag", "rkl_stream",
 ]
 
@@ -104,6 +105,7 @@ def load(build_if_missing: bool = True):
         "rkl_batch_policy_count": (i32, []),
         "rkl_batch_policy_info": (i32, [i32, P(i32), P(i32)]),
         "rkl_set_batch_policy": (i32, [vp, i32]),
+        "rkl_set_batch_mode": (i32, [vp, i32]),
         "rkl_autotune_batched": (i32, [vp, vp, vp, vp, i32, P(i32), P(dbl), vp]),
         "rkl_subcycle": (i32, [vp, i32, vp, vp, dbl, i64, P(i64), vp]),
         "rkl_aag": (i32, [vp, i32, vp, vp, dbl, dbl, i32, P(i32), vp]),
@@ -245,6 +247,10 @@ def rkl_batch_policy_info(policy):
 
 def rkl_set_batch_policy(plan, policy):
     _check(load().rkl_set_batch_policy(plan, policy))
+
+
+def rkl_set_batch_mode(plan, mode):
+    _check(load().rkl_set_batch_mode(plan, int(mode)))
 
 
 def rkl_autotune_batched(plan, T_ptr, b_ptr, dt_ptr, reps, stream):
@@ -402,6 +408,10 @@ class Plan:
 
     def set_batch_policy(self, policy):
         rkl_set_batch_policy(self.handle, policy)
+
+    def set_batch_mode(self, mode):
+        """0: one launch per stage; 1: one persistent launch (see rkl.h)."""
+        rkl_set_batch_mode(self.handle, mode)
 
     def autotune_batched(self, T, b, dt_hyp, reps=2):
         """Pick the fastest batched tile policy by timing; returns (policy, ms)."""

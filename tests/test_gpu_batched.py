@@ -89,12 +89,82 @@ def test_batched_equals_single_grid_calls(torch_cuda):
         assert torch.equal(Tp, T[off[p]:off[p + 1]]), p
 
 
-@pytest.mark.skip(reason="the single persistent launch with per-grid stage-dependency counters "
-                         "(work queues, agent-scope release/acquire between workgroups) did not "
-                         "finish on the MI355X; its cause is not shown, so that code path is "
-                         "removed and the batched super-step uses one launch per stage")
-def test_persistent_equals_per_stage_launches():
-    pass
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_persistent_equals_per_stage_launches(torch_cuda, precision, tol):
+    """The persistent launch (rkl_set_batch_mode 1: reduce, schedule and one
+    persistent launch whose workgroups take (stage, grid, tile) items from a
+    ticket counter) gives the same bits as one launch per stage, and matches
+    the oracle; eager and graph-captured, three super-steps; no wait gave up."""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    ps = small_patch_set(24, seed=13, lo=8, hi=40, smin=2, smax=14)
+    print("persistent", precision, ps.n[:4], flush=True)
+    ref, sref, dts = oracle_patches(ps, precision)
+    per = make_plan(ps, precision)
+    pers = make_plan(ps, precision)
+    pers.set_batch_mode(1)
+    Ta, b = pack(torch, ps, precision)
+    Tb, Tc = Ta.clone(), Ta.clone()
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda:0")
+    sa = torch.zeros(len(ps.n), dtype=torch.int32, device="cuda:0")
+    sb = torch.zeros_like(sa)
+    per.superstep_batched(Ta, b, dt, sa)
+    pers.superstep_batched(Tb, b, dt, sb)
+    torch.cuda.synchronize()
+    assert all(pers.query(p)[2] & rkl.RKL_FLAG_ABORTED == 0 for p in range(len(ps.n)))
+    assert torch.equal(sa, sb) and list(sb.cpu().numpy()) == sref
+    assert torch.equal(Ta, Tb)
+    got = Tb.cpu().numpy()
+    off = per.offsets()
+    for p in range(len(ps.n)):
+        assert rel_l1(got[off[p]:off[p + 1]].reshape(ref[p].shape), ref[p]) <= tol, p
+    # two more super-steps, eager per-stage launches against the persistent graph
+    pers.graph_capture(Tc, b, dt, sb)
+    pers.graph_launch()                      # Tc: first super-step
+    assert torch.equal(Tc, Ta)
+    for _ in range(2):
+        per.superstep_batched(Ta, b, dt, sa)
+        pers.graph_launch()
+        torch.cuda.synchronize()
+        assert torch.equal(Tc, Ta) and torch.equal(sa, sb)
+    assert all(pers.query(p)[2] & rkl.RKL_FLAG_ABORTED == 0 for p in range(len(ps.n)))
+    per.close()
+    pers.close()
+
+
+def test_persistent_patch_workload(torch_cuda):
+    """The 2000 patches: two super-steps of the persistent launch equal the
+    per-stage launches bit for bit (mixed precision); timings printed."""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    ps = inputs.patch_set(2000, device="cuda:0")
+    T0 = torch.cat([t.reshape(-1) for t in ps.T]).contiguous()
+    b = torch.cat([x.reshape(-1) for x in ps.b]).float().contiguous()
+    ps.T = ps.b = None
+    descs = [lib_desc(n, (1 / 64,) * 3, 3, ps.params) for n in ps.n]
+    out = {}
+    for mode in (0, 1):
+        plan = rkl.Plan(descs, precision="mixed", smax=48)
+        plan.set_batch_mode(mode)
+        off = plan.offsets()
+        dt = torch.tensor([ps.ratio[k] * plan.dt_par(T0[off[k]:off[k + 1]], grid=k) for k in range(len(descs))],
+                          dtype=torch.float64, device="cuda:0")
+        T = T0.clone()
+        s_out = torch.zeros(len(descs), dtype=torch.int32, device="cuda:0")
+        plan.graph_capture(T, b, dt, s_out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
+            plan.graph_launch()
+        e1.record()
+        torch.cuda.synchronize()
+        flags = max(plan.query(k)[2] for k in range(0, len(descs), 50))
+        print("mode %d: %.2f ms per super-step, flags %d" % (mode, e0.elapsed_time(e1) / 2, flags), flush=True)
+        assert flags & rkl.RKL_FLAG_ABORTED == 0
+        out[mode] = (T.clone(), s_out.clone())
+        plan.close()
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][0], out[1][0])
 
 
 def test_many_supersteps_match_oracle(torch_cuda):
@@ -268,7 +338,8 @@ def test_batched_autotune(torch_cuda):
     T_before = T.clone()
     pol, ms = plan.autotune_batched(T, b, dt, reps=1)
     assert torch.equal(T, T_before)              # the caller's T is not touched
-    assert 0 <= pol < rkl.rkl_batch_policy_count() and ms > 0
+    # index = tile policy + launch mode x policy count (both modes are timed)
+    assert 0 <= pol < 2 * rkl.rkl_batch_policy_count() and ms > 0
     plan.superstep_batched(T, b, dt)
     got = T.cpu().numpy()
     off = plan.offsets()

@@ -1,0 +1,265 @@
+"""The library against the oracle element by element on identical inputs:
+whole fields, and whole workload horizons.
+
+Two errors are reported for mixed precision (FP32 flux, FP64 stage
+recurrence; the unit vectors are stored in FP32):
+  arithmetic-only -- against the oracle fed the same FP32-rounded unit
+    vectors, so that only the arithmetic differs (the bar: rel-L1 <= 1e-5);
+  against the FP64 problem -- against the oracle fed the FP64 unit vectors,
+    which adds the rounding of b to FP32 (printed).
+FP64 runs are held to rel-L1 <= 1e-12 against the oracle.  Stage counts must
+agree at every super-step; a divergence is counted, printed and kept in the
+error, never dropped.
+
+Over a horizon of several super-steps the MC-limited RKL2 update can amplify
+rounding-size differences about tenfold per super-step (the limited
+operator is nonlinear; tests/test_oracle_conditioning.py shows it with the
+oracle alone).  Where that happens the FP64 library, whose operations differ
+from the oracle's only in their order, also leaves 1e-12 behind: then no
+implementation can be held to a fixed bar over the whole horizon.  So the
+bars are applied at every super-step while the FP64 library is still within
+its own 1e-12 of the oracle -- on the full-size 256^3 workload that is the
+whole horizon -- and the rest is printed.
+
+Cases:
+  - the 256^3 workload, one super-step, every cell (FP64 and mixed);
+  - the 256^3 workload over its whole horizon (10 super-steps), every cell;
+  - the 256^3, 512^3 saturated and 768^3 saturated workloads with their
+    continuous fields sampled at 64^3 (same parameters, stage counts and
+    super-step counts), every cell over every super-step;
+  - the 2000 patches, one batched super-step, every cell of every patch;
+  - the 2000 patches over their horizon (10 super-steps of the captured
+    graph) on a sample of patches that includes every patch whose stage
+    count differs at some super-step between the mixed and FP64 library runs.
+The oracle runs on up to 16 threads (the same bits as serial)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import lib_desc, oracle_grid, rel_l1
+from paper_1702_05487_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1702_05487_amd import rkl
+    rkl.load(build_if_missing=False)
+    oracle.set_threads(min(16, len(os.sched_getaffinity(0))))
+    yield torch
+    oracle.set_threads(1)
+
+
+def lib_run(torch, n, ndim, params, precision, T0, b, ratio, steps):
+    """`steps` library super-steps at dt_hyp = ratio * dt_par(T0) on the
+    periodic unit box; returns (T after every step, stage counts, dt_hyp)."""
+    from paper_1702_05487_amd import rkl
+    h = tuple(1.0 / v for v in n)
+    plan = rkl.Plan([lib_desc(n, h, ndim, params)], precision=precision)
+    T = torch.from_numpy(np.ascontiguousarray(T0)).to("cuda:0")
+    bd = b.astype(np.float32) if precision == "mixed" else b
+    bg = torch.from_numpy(np.ascontiguousarray(bd)).to("cuda:0")
+    dt = ratio * plan.dt_par(T)
+    outs, ss = [], []
+    for _ in range(steps):
+        ss.append(plan.superstep(T, bg, dt))
+        outs.append(T.cpu().numpy())
+    plan.close()
+    return outs, ss, dt
+
+
+def oracle_run(n, ndim, params, T0, b, dt, steps, h=None):
+    g = oracle_grid(n, h or tuple(1.0 / v for v in n), ndim, params)
+    T, outs, ss = T0, [], []
+    for _ in range(steps):
+        T, s, _ = oracle.superstep(g, T, b, dt)
+        outs.append(T)
+        ss.append(s)
+    return outs, ss
+
+
+def fmt(v):
+    return " ".join("%.1e" % x for x in v)
+
+
+def check_horizon(label, e64, ea, ep):
+    """Bars at every super-step while the FP64 library is within 1e-12 of the
+    oracle (and at the first super-step always); returns how many steps that is."""
+    ok = 0
+    while ok < len(e64) and e64[ok] <= 1e-12:
+        ok += 1
+    print("  %s: FP64 rel-L1 per step %s" % (label, fmt(e64)))
+    print("  %s: mixed arithmetic-only rel-L1 per step %s" % (label, fmt(ea)))
+    print("  %s: mixed against the FP64 problem rel-L1 per step %s" % (label, fmt(ep)))
+    print("  %s: FP64 within 1e-12 of the oracle for the first %d of %d super-steps" % (label, ok, len(e64)))
+    assert e64[0] <= 1e-12 and ea[0] <= 1e-5
+    assert max(ea[:ok], default=0.0) <= 1e-5
+    return ok
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_256_whole_field_one_superstep(torch_cuda, precision):
+    torch = torch_cuda
+    w = inputs.spitzer_256(fields=False)
+    T0 = inputs.noisy_temperature(w.n, 2)
+    b = inputs.tangled_b(w.n, 1)
+    got, s_lib, dt = lib_run(torch, w.n, 3, w.params, precision, T0, b, w.ratio, 1)
+    bo = b.astype(np.float32).astype(np.float64) if precision == "mixed" else b
+    ref, s_ref = oracle_run(w.n, 3, w.params, T0, bo, dt, 1)
+    err = rel_l1(got[0], ref[0])
+    chg = float(np.abs((got[0] - T0) - (ref[0] - T0)).sum() / np.abs(ref[0] - T0).sum())
+    print("256^3 %s, one super-step, all %d cells: s %s/%s, rel-L1 %.3e, Linf %.3e, rel-L1 of the change %.3e"
+          % (precision, T0.size, s_lib, s_ref, err, float(np.abs(got[0] - ref[0]).max()), chg))
+    assert s_lib == s_ref == [16]
+    assert err <= (1e-12 if precision == "fp64" else 1e-5)
+
+
+def horizon_case(torch, name, n):
+    w = getattr(inputs, name)(fields=False)
+    T0 = inputs.noisy_temperature(n, 2)
+    b = inputs.tangled_b(n, 1)
+    b32 = b.astype(np.float32).astype(np.float64)
+    lib64, s64, dt64 = lib_run(torch, n, 3, w.params, "fp64", T0, b, w.ratio, w.steps)
+    lib32, s32, dt32 = lib_run(torch, n, 3, w.params, "mixed", T0, b, w.ratio, w.steps)
+    assert dt64 == dt32
+    ref64, sr64 = oracle_run(n, 3, w.params, T0, b, dt64, w.steps)
+    ref32, sr32 = oracle_run(n, 3, w.params, T0, b32, dt64, w.steps)
+    label = "%s at %dx%dx%d" % (name, *n)
+    print("%s, %d super-steps: stages FP64 %s (oracle %s), mixed %s (oracle, FP32 b: %s); "
+          "mixed Linf at the end %.3e (arithmetic only), %.3e (FP64 problem)"
+          % (label, w.steps, s64, sr64, s32, sr32, float(np.abs(lib32[-1] - ref32[-1]).max()),
+             float(np.abs(lib32[-1] - ref64[-1]).max())))
+    assert s64 == sr64 and s32 == sr32
+    e64 = [rel_l1(a, r) for a, r in zip(lib64, ref64)]
+    ea = [rel_l1(a, r) for a, r in zip(lib32, ref32)]
+    ep = [rel_l1(a, r) for a, r in zip(lib32, ref64)]
+    return label, e64, ea, ep
+
+
+def test_256_whole_horizon(torch_cuda):
+    # the full-size workload: every cell after every one of its 10 super-steps
+    label, e64, ea, ep = horizon_case(torch_cuda, "spitzer_256", (256, 256, 256))
+    ok = check_horizon(label, e64, ea, ep)
+    assert ok == len(e64)          # the bars hold over the whole horizon
+
+
+@pytest.mark.parametrize("name", ["spitzer_256", "saturated_512", "fused_768"])
+def test_workload_horizon_at_64(torch_cuda, name):
+    label, e64, ea, ep = horizon_case(torch_cuda, name, (64, 64, 64))
+    ok = check_horizon(label, e64, ea, ep)
+    assert ok >= 3
+    if ok < len(e64):
+        # the problem amplifies the FP64 library's rounding-order differences
+        # (~1e-15 at the first super-step) by orders of magnitude
+        assert max(e64) >= 100.0 * e64[0]
+
+
+def patch_runs(torch, ps, T0, b64, steps, keep_every_step):
+    from paper_1702_05487_amd import rkl
+    descs = [lib_desc(n, (1 / 64,) * 3, 3, ps.params) for n in ps.n]
+    runs = {}
+    for precision in ("fp64", "mixed"):
+        b = b64.float().contiguous() if precision == "mixed" else b64
+        plan = rkl.Plan(descs, precision=precision, smax=48)
+        off = plan.offsets()
+        dt = torch.tensor([ps.ratio[k] * plan.dt_par(T0[off[k]:off[k + 1]], grid=k) for k in range(len(descs))],
+                          dtype=torch.float64, device="cuda:0")
+        T = T0.clone()
+        s_out = torch.zeros(len(descs), dtype=torch.int32, device="cuda:0")
+        plan.graph_capture(T, b, dt, s_out)
+        hist, Ts = [], []
+        for _ in range(steps):
+            plan.graph_launch()
+            hist.append(s_out.cpu().numpy().copy())
+            if keep_every_step:
+                Ts.append(T.clone())
+        flags = max(plan.query(k)[2] for k in range(len(descs)))
+        assert flags == 0
+        runs[precision] = (Ts if keep_every_step else [T], np.array(hist), dt.cpu().numpy())
+        plan.close()
+    assert np.array_equal(runs["fp64"][2], runs["mixed"][2])
+    return runs, off
+
+
+def patch_fields(torch):
+    ps = inputs.patch_set(2000, device="cuda:0")
+    T0 = torch.cat([t.reshape(-1) for t in ps.T]).contiguous()
+    b64 = torch.cat([x.reshape(-1) for x in ps.b]).contiguous()
+    ps.T = ps.b = None
+    return ps, T0, b64
+
+
+def test_patches_one_superstep_every_cell(torch_cuda):
+    # mixed batched graph, all 2000 patches, one super-step, every cell
+    torch = torch_cuda
+    ps, T0, b64 = patch_fields(torch)
+    runs, off = patch_runs(torch, ps, T0, b64, 1, False)
+    T0h, bh = T0.cpu().numpy(), b64.cpu().numpy()
+    got = runs["mixed"][0][0].cpu().numpy()
+    s_lib = runs["mixed"][1][0]
+    dts = runs["mixed"][2]
+    num = den = linf = worst = 0.0
+    sdiv = []
+    for k, n in enumerate(ps.n):
+        sl = slice(off[k], off[k + 1])
+        shape = (n[2], n[1], n[0])
+        bk = bh[3 * off[k]:3 * off[k + 1]].reshape((3,) + shape).astype(np.float32).astype(np.float64)
+        ref, sr = oracle_run(n, 3, ps.params, T0h[sl].reshape(shape), bk, dts[k], 1, h=(1 / 64,) * 3)
+        d = np.abs(got[sl].reshape(shape) - ref[0])
+        num += float(d.sum())
+        den += float(np.abs(ref[0]).sum())
+        linf = max(linf, float(d.max()))
+        worst = max(worst, float(d.sum() / np.abs(ref[0]).sum()))
+        if sr[0] != s_lib[k]:
+            sdiv.append(k)
+    print("2000 patches, one mixed batched super-step, all %d cells: rel-L1 %.3e, worst patch %.3e, Linf %.3e, "
+          "stage counts differ for %d patches" % (int(sum(ps.cells)), num / den, worst, linf, len(sdiv)))
+    assert not sdiv
+    assert num / den <= 1e-5 and worst <= 1e-5
+
+
+def test_patches_horizon_against_the_oracle(torch_cuda):
+    torch = torch_cuda
+    ps, T0, b64 = patch_fields(torch)
+    runs, off = patch_runs(torch, ps, T0, b64, 10, True)
+    T0h, bh = T0.cpu().numpy(), b64.cpu().numpy()
+    dts = runs["fp64"][2]
+    # sample: every patch whose stage count differs between the two library
+    # runs at some super-step, 24 drawn at random, and the 4 with most cells
+    div = np.nonzero(np.any(runs["fp64"][1] != runs["mixed"][1], axis=0))[0].tolist()
+    rng = np.random.default_rng(5)
+    big = np.argsort([-c for c in ps.cells])[:4].tolist()
+    sample = sorted(set(div) | set(rng.choice(2000, 24, replace=False).tolist()) | set(big))
+    print("2000 patches, 10 super-steps: %d patches change stage count between the FP64 and mixed library runs; "
+          "sample of %d patches" % (len(div), len(sample)), flush=True)
+    steps = 10
+    num64, numa, nump, den = np.zeros(steps), np.zeros(steps), np.zeros(steps), np.zeros(steps)
+    sdiv64, sdiva = [], []
+    for k in sample:
+        n = ps.n[k]
+        shape = (n[2], n[1], n[0])
+        sl = slice(off[k], off[k + 1])
+        Tk = T0h[sl].reshape(shape)
+        bk = bh[3 * off[k]:3 * off[k + 1]].reshape((3,) + shape)
+        ref64, sr64 = oracle_run(n, 3, ps.params, Tk, bk, dts[k], steps, h=(1 / 64,) * 3)
+        ref32, sr32 = oracle_run(n, 3, ps.params, Tk, bk.astype(np.float32).astype(np.float64), dts[k], steps,
+                                 h=(1 / 64,) * 3)
+        if list(runs["fp64"][1][:, k]) != sr64:
+            sdiv64.append(k)
+        if list(runs["mixed"][1][:, k]) != sr32:
+            sdiva.append(k)
+        for j in range(steps):
+            g64 = runs["fp64"][0][j][sl].cpu().numpy().reshape(shape)
+            g32 = runs["mixed"][0][j][sl].cpu().numpy().reshape(shape)
+            num64[j] += float(np.abs(g64 - ref64[j]).sum())
+            numa[j] += float(np.abs(g32 - ref32[j]).sum())
+            nump[j] += float(np.abs(g32 - ref64[j]).sum())
+            den[j] += float(np.abs(ref64[j]).sum())
+    print("  stage counts differ from the oracle's at some super-step: FP64 %d patches %s, mixed %d patches %s"
+          % (len(sdiv64), sdiv64, len(sdiva), sdiva))
+    check_horizon("2000 patches, sample of %d" % len(sample), list(num64 / den), list(numa / den), list(nump / den))
