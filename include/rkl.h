@@ -189,6 +189,27 @@ rkl_status rkl_superstep_async(rkl_plan_t plan, int32_t grid, double *T, const v
                                int32_t s_cap, int32_t *s_out, void *stream);
 
 /*
+ * rkl_superstep_noalloc: for callers that cannot allocate device memory --
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The super-step of rkl_superstep_async (RKL2, s on the device,
+ * s_cap stage launches, no host synchronisation) on one grid described by
+ * *grid, with no plan and no allocation of any kind: its scratch is a static
+ * device array inside the library, 8 B x 3 x RKL_NOALLOC_MAX_CELLS plus a
+ * few KB (50.4 MB), held by each GPU the library runs on until the process
+ * ends.  precision: RKL_FP64 or RKL_MIXED (b double or float accordingly).
+ * Limits: at most RKL_NOALLOC_MAX_CELLS cells and s_cap in [2,
+ * RKL_NOALLOC_MAX_STAGES]; larger requests return RKL_EINVAL with a message.
+ * s_out: device int32 (may be NULL) receiving s; if s > s_cap, T is left
+ * unchanged (s_out tells).  Stencil variant 0.  Every call on one GPU shares
+ * that GPU's scratch, so calls that overlap on one GPU (two streams or host
+ * threads at once) race; serialise them.
+ */
+#define RKL_NOALLOC_MAX_CELLS 2097152   /* 2^21, e.g. 128^3 */
+#define RKL_NOALLOC_MAX_STAGES 256
+rkl_status rkl_superstep_noalloc(const rkl_grid_desc *grid, int32_t precision, double *T, const void *b,
+                                 double dt_hyp, int32_t s_cap, int32_t *s_out, void *stream);
+
+/*
  * rkl_subcycle: explicit sub-cycling of the conduction operator over dt_hyp
  * on one grid, T updated in place (Sec. 2.3, the sub-cycled alternative the
  * paper compares super-time-stepping with): N_sub = ceil(dt_hyp / dt_par)

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librkl.so")
-SOURCES = ["rkl_kernels.hip", "rkl_fused.hip", "rkl_batch.hip", "rkl_api.hip", "rkl_stream.hip"]
+SOURCES = ["rkl_kernels.hip", "rkl_fused.hip", "rkl_batch.hip", "rkl_api.hip", "rkl_noalloc.hip", "rkl_stream.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -25,7 +25,7 @@ RKL_FLAG_NONPOS, RKL_FLAG_NONFINITE, RKL_FLAG_STAGES, RKL_FLAG_ABORTED = 1, 2, 4
 
 EXPORTS = [
     "rkl_plan", "rkl_destroy", "rkl_grid_offset", "rkl_flux_div", "rkl_dt_par",
-    "rkl_superstep", "rkl_superstep_async", "rkl_superstep_batched", "rkl_graph_capture", "rkl_graph_launch",
+    "rkl_superstep", "rkl_superstep_async", "rkl_superstep_noalloc", "rkl_superstep_batched", "rkl_graph_capture", "rkl_graph_launch",
     "rkl_query", "rkl_variant_count", "rkl_variant_info", "rkl_set_variant", "rkl_last_error",
     "rkl_profile", "rkl_profile_read", "rkl_autotune",
     "rkl_batch_policy_count", "rkl_batch_policy_info", "rkl_set_batch_policy", "rkl_autotune_batched",
@@ -91,6 +91,7 @@ def load(build_if_missing: bool = True):
         "rkl_dt_par": (i32, [vp, i32, vp, P(dbl), vp]),
         "rkl_superstep": (i32, [vp, i32, vp, vp, dbl, P(i32), vp]),
         "rkl_superstep_async": (i32, [vp, i32, vp, vp, dbl, i32, vp, vp]),
+        "rkl_superstep_noalloc": (i32, [P(rkl_grid_desc), i32, vp, vp, dbl, i32, vp, vp]),
         "rkl_superstep_batched": (i32, [vp, vp, vp, vp, vp, vp]),
         "rkl_graph_capture": (i32, [vp, vp, vp, vp, vp, vp]),
         "rkl_graph_launch": (i32, [vp, vp]),
@@ -159,6 +160,27 @@ def rkl_superstep(plan, grid, T_ptr, b_ptr, dt_hyp, stream):
 
 def rkl_superstep_async(plan, grid, T_ptr, b_ptr, dt_hyp, s_cap, s_ptr, stream):
     _check(load().rkl_superstep_async(plan, grid, T_ptr, b_ptr, float(dt_hyp), int(s_cap), s_ptr, stream))
+
+
+NOALLOC_MAX_CELLS = 2097152
+NOALLOC_MAX_STAGES = 256
+
+
+def rkl_superstep_noalloc(desc, precision, T_ptr, b_ptr, dt_hyp, s_cap, s_ptr, stream):
+    _check(load().rkl_superstep_noalloc(ctypes.byref(desc), int(precision), T_ptr, b_ptr, float(dt_hyp),
+                                        int(s_cap), s_ptr, stream))
+
+
+def superstep_noalloc(desc, T, b, dt_hyp, s_cap, s_out=None, precision="fp64"):
+    """One allocation-free super-step of the grid `desc` on torch tensors
+    (T in place; s lands in the int32 device tensor s_out)."""
+    import torch
+    prec = RKL_MIXED if precision in ("mixed", RKL_MIXED) else RKL_FP64
+    n = desc.n[0] * desc.n[1] * desc.n[2]
+    tp = _dev_ptr(T, torch.float64, n, "T")
+    bp = _dev_ptr(b, torch.float32 if prec == RKL_MIXED else torch.float64, 3 * n, "b")
+    sp = None if s_out is None else _dev_ptr(s_out, torch.int32, 1, "s_out")
+    rkl_superstep_noalloc(desc, prec, tp, bp, dt_hyp, s_cap, sp, _stream())
 
 
 def rkl_subcycle(plan, grid, T_ptr, b_ptr, dt_hyp, max_sub, stream):

@@ -146,3 +146,21 @@ int main(void) {
     assert out.returncode == 0, (out.returncode, out.stderr)
     n, fused = (int(x) for x in out.stdout.split())
     assert n == rkl.rkl_variant_count() and fused >= 1
+
+
+def test_noalloc_refuses_sizes_beyond_its_static_scratch():
+    # checked on the host before any device call
+    import ctypes
+    big = rkl.grid_desc((128, 128, 129), (0.01, 0.01, 0.01), ndim=3)
+    with pytest.raises(rkl.RklError) as e:
+        rkl.rkl_superstep_noalloc(big, rkl.RKL_FP64, ctypes.c_void_p(256), ctypes.c_void_p(4096), 1e-6, 8,
+                                  None, None)
+    assert e.value.status == rkl.RKL_EINVAL and "RKL_NOALLOC_MAX_CELLS" in str(e.value)
+    small = rkl.grid_desc((8, 8, 8), (0.1, 0.1, 0.1), ndim=3)
+    for cap in (1, rkl.NOALLOC_MAX_STAGES + 1):
+        with pytest.raises(rkl.RklError) as e:
+            rkl.rkl_superstep_noalloc(small, rkl.RKL_FP64, ctypes.c_void_p(256), ctypes.c_void_p(4096), 1e-6,
+                                      cap, None, None)
+        assert "RKL_NOALLOC_MAX_STAGES" in str(e.value)
+    with pytest.raises(rkl.RklError):
+        rkl.rkl_superstep_noalloc(small, 7, ctypes.c_void_p(256), ctypes.c_void_p(4096), 1e-6, 8, None, None)
