@@ -47,24 +47,27 @@ WORKLOADS = {
     "patches_2000_fp64_loop": ("patch_set", "fp64"),   # plain FP64: one rkl_superstep per patch
     "spitzer_256_subcycle": ("spitzer_256", "fp64"),   # explicit sub-cycling over the same dt_hyp
 }
+_FUSED_SOURCES = ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_fused.h",
+                  "paper_1702_05487_amd/csrc/rkl_fused.hip"]
 KERNEL_SOURCES = {
     1: ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_stage.h",
         "paper_1702_05487_amd/csrc/rkl_kernels.hip"],
-    2: ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_fused.h",
-        "paper_1702_05487_amd/csrc/rkl_fused.hip"],
+    2: _FUSED_SOURCES, 3: _FUSED_SOURCES, 4: _FUSED_SOURCES,
     "batch": ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_batch.hip"],
 }
-KERNEL_NAMES = {1: "stage_kernel", 2: "fused2_kernel", "batch": "batch_stage_kernel"}
+KERNEL_NAMES = {1: "stage_kernel", 2: "fused_kernel", 3: "fused_kernel", 4: "fused_kernel",
+                "batch": "batch_stage_kernel"}
 
 
 def bytes_per_cell_stage(precision, fuse):
     """Algorithmic HBM bytes per cell and stage of the dominant kernel.
     One stage j >= 2 reads Y_{j-1}, Y_{j-2}, Y0 (FP64), tau M(Y0) and the
     three components of b (FP64, or FP32 in mixed precision) and writes Y_j:
-    64 B (FP64) or 48 B (mixed).  A two-stage launch reads the same inputs
-    once and writes Y_j and Y_{j+1}: 56 B per cell for two stages."""
-    if fuse == 2:
-        return 28.0
+    64 B (FP64) or 48 B (mixed).  A launch of F fused stages (mixed) reads
+    the same inputs once and writes the last two stage values: 56 B per cell
+    for F stages."""
+    if fuse >= 2:
+        return 56.0 / fuse
     return 64.0 if precision == "fp64" else 48.0
 
 
@@ -279,7 +282,7 @@ def bench_batched(args, torch, inputs, rkl, precision="mixed", loop=False):
         rkl.rkl_profile(plan.handle, 1)
         plan.superstep_batched(T, b, dt, s_out)
         persistent = policy // rkl.rkl_batch_policy_count() == 1
-        ms, launches, _ = rkl.rkl_profile_read(plan.handle, 4 if persistent else 1)
+        ms, launches, _ = rkl.rkl_profile_read(plan.handle, 6 if persistent else 1)
         rkl.rkl_profile(plan.handle, 0)
         s1 = s_out.cpu().numpy().astype(np.int64)
         if persistent:
@@ -429,7 +432,7 @@ def bench_subcycle(args, torch, inputs, rkl):
     sec_aag, stages_aag = timed(lambda: plan.aag(T, b, dt, 0.01))
     rkl.rkl_profile(plan.handle, 1)
     sec_sub, nsub = timed(lambda: plan.subcycle(T, b, dt))
-    ms, launches, _ = rkl.rkl_profile_read(plan.handle, 3)
+    ms, launches, _ = rkl.rkl_profile_read(plan.handle, 5)
     rkl.rkl_profile(plan.handle, 0)
     dtp = plan.dt_par(T0)
     sweep = []

@@ -275,11 +275,13 @@ rkl_status rkl_query(rkl_plan_t plan, int32_t grid, int32_t *last_s, double *las
  * fills the workgroup tile (tile_x x tile_y cells, a z-chunk of tile_z
  * planes) and the stages per launch `fuse` (any pointer may be NULL):
  *   fuse 1: one RKL2 stage per launch, output tile = tile_x x tile_y;
- *   fuse 2: stages j and j+1 in one launch (temporal fusion of Appendix A's
- *           recurrence; 2 <= j, j+1 < s, the last stage always runs alone),
- *           output tile (tile_x-2) x (tile_y-2): the tile's border ring is
- *           recomputed by the neighbouring tiles.  RKL_MIXED plans of periodic 3-D
- *           grids only; selecting one allocates two more FP64 stage buffers.
+ *   fuse F = 2, 3, 4: stages j..j+F-1 in one launch (temporal fusion of
+ *           Appendix A's recurrence; 2 <= j, j+F-1 < s; the last stage, and a
+ *           remainder shorter than F, run one stage per launch), output tile
+ *           (tile_x-2(F-1)) x (tile_y-2(F-1)): the tile's border rings are
+ *           recomputed by the neighbouring tiles.  RKL_MIXED plans of periodic
+ *           3-D grids only; selecting one allocates two more FP64 stage
+ *           buffers.
  * rkl_set_variant selects a variant for a plan (RKL_EINVAL if the plan
  * cannot use it, RKL_ENOMEM); the autotuner calls it.
  */
@@ -296,8 +298,9 @@ rkl_status rkl_set_variant(rkl_plan_t plan, int32_t variant);
  * launch of rkl_subcycle and rkl_aag; rkl_profile(plan, 0) stops and
  * discards.
  * rkl_profile_read synchronises and returns, over the launches of one kind
- * -- `fuse` 1: one-stage, 2: two-stage, 3: forward-Euler sub-steps, 4: the
- * persistent batched launch (all stages of a super-step) -- the summed
+ * -- `fuse` 1: one stage per launch, 2..4: that many fused stages, 5:
+ * forward-Euler sub-steps, 6: the persistent batched launch (all stages of a
+ * super-step) -- the summed
  * duration in ms, the number of launches and of cell updates (batched
  * launches count 0: their work follows from the device-side stage counts).
  */

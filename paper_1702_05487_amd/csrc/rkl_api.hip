@@ -340,8 +340,9 @@ rkl_status rkl_variant_info(int32_t v, int32_t* tx, int32_t* ty, int32_t* tz, in
     return RKL_OK;
 }
 
-// A two-stage variant needs RKL_MIXED and periodic 3-D grids, and two more
-// stage buffers (tiles overlap, so its outputs may not overwrite its inputs).
+// A fused variant (2 to 4 stages per launch) needs RKL_MIXED and periodic
+// 3-D grids, and two more stage buffers (tiles overlap, so its outputs may
+// not overwrite its inputs).
 static bool fused_ok(const rkl_plan_s* p) {
     if (p->precision != RKL_MIXED) return false;
     for (const auto& d : p->desc)
@@ -350,13 +351,13 @@ static bool fused_ok(const rkl_plan_s* p) {
 }
 
 static bool variant_ok(const rkl_plan_s* p, const Variant& x) {
-    return x.fuse == 2 ? fused_ok(p) : true;
+    return x.fuse >= 2 ? fused_ok(p) : true;
 }
 
 static rkl_status select_variant(rkl_plan_s* p, int v) {
     const Variant x = variant_get(v);
-    if (x.fuse == 2) {
-        if (!fused_ok(p)) return fail(RKL_EINVAL, "two-stage variants need an RKL_MIXED plan of periodic 3-D grids");
+    if (x.fuse >= 2) {
+        if (!fused_ok(p)) return fail(RKL_EINVAL, "fused variants need an RKL_MIXED plan of periodic 3-D grids");
         if (!p->Yc) {
             if (hipMalloc(&p->Yc, sizeof(double) * p->total) != hipSuccess ||
                 hipMalloc(&p->Yd, sizeof(double) * p->total) != hipSuccess) {
@@ -564,15 +565,16 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
             HIPCHECK(hipEventRecord(e0, s), "event record");
         }
         int done;
-        if (v.fuse == 2 && j + 1 < S) {
-            // stages j, j+1 in one launch; the final stage always runs alone
-            // (it writes T, which the fused kernel reads around its tiles)
+        if (v.fuse >= 2 && j + v.fuse - 1 < S) {
+            // stages j..j+F-1 in one launch, writing Y_{j+F-2} and Y_{j+F-1};
+            // the final stage always runs alone (it writes T, which the fused
+            // kernel reads around its tiles), and so does a shorter remainder
             double* o1 = pick(ym1, ym2, nullptr);
             double* o2 = pick(ym1, ym2, o1);
-            HIPCHECK(launch_fused2(v, gc, j, ym1, ym2, T, M, o1, o2, b, gs, p->coef, s), "fused stage launch");
+            HIPCHECK(launch_fused(v, gc, j, ym1, ym2, T, M, o1, o2, b, gs, p->coef, s), "fused stage launch");
             ym2 = o1;
             ym1 = o2;
-            done = 2;
+            done = v.fuse;
         } else {
             // Y_j overwrites Y_{j-2} cell by cell (never Y0 = T before the last stage)
             double* out = j == S ? T : (ym2 == T ? pick(ym1, T, nullptr) : const_cast<double*>(ym2));
@@ -650,7 +652,7 @@ static rkl_status euler_substeps(rkl_plan_t p, int32_t g, double* T, const void*
                  "sub-step launch");
         if (p->prof) {
             HIPCHECK(hipEventRecord(e1, s), "event record");
-            p->prof_recs[rec].fuse = 3;
+            p->prof_recs[rec].fuse = 5;
             p->prof_recs[rec].cells = n;
         }
     }
@@ -801,7 +803,7 @@ rkl_status rkl_profile(rkl_plan_t p, int32_t enable) {
 
 rkl_status rkl_profile_read(rkl_plan_t p, int32_t fuse, double* ms, int64_t* launches, int64_t* cells) {
     if (rkl_status st = check_plan(p)) return st;
-    if (fuse < 1 || fuse > 4) return fail(RKL_EINVAL, "fuse must be 1, 2, 3 or 4");
+    if (fuse < 1 || fuse > 6) return fail(RKL_EINVAL, "kind must be 1 to 6");
     double tot = 0.0;
     int64_t nl = 0, nc = 0;
     for (const auto& r : p->prof_recs) {
@@ -845,8 +847,8 @@ rkl_status rkl_superstep_batched(rkl_plan_t p, double* T, const void* b, const d
     hipError_t e = batch_launch(p->batch, bb, (hipStream_t)stream, p->prof ? &ev : nullptr, p->batch_mode);
     // cell-stages of a batched launch depend on the device-side stage counts:
     // recorded as 0 (the caller knows them from s_out); the persistent launch
-    // is recorded as kind 4
-    for (auto& x : ev) p->prof_recs.push_back({x.first, x.second, p->batch_mode == 1 ? 4 : 1, 0});
+    // is recorded as kind 6
+    for (auto& x : ev) p->prof_recs.push_back({x.first, x.second, p->batch_mode == 1 ? 6 : 1, 0});
     if (e != hipSuccess) return hipfail(e, "batched launch");
     return RKL_OK;
 }

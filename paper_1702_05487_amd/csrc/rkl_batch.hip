@@ -214,42 +214,80 @@ __global__ __launch_bounds__(kBT) void batch_stage_kernel(BatchBufs P, const int
     batch_tile<R, LIM, SAT, KM>(P, it.x, stage, it.y, st, L);
 }
 
-// Schedule of the persistent launch (one workgroup).  Thread 0 orders the
-// grids by stage count, largest first (stable over the largest-grid-first
-// order), counts for every stage j the grids that reach it, cnt(j), and lays
-// the stages out one after another: stage j's items are the tiles of the
-// first cnt(j) grids of that order, i.e. a prefix of one list of all tiles in
-// that order, and start at ticket base[j].  Grids flagged at the reduce step
-// (s above smax, or a bad dt_hyp) have no items.  The workgroup then writes
-// the tile list.
+// Schedule of the persistent launch (one workgroup).  The grids are ordered
+// by stage count, largest first, stable over the largest-grid-first order
+// (a counting sort: histogram, bucket starts, then the grids in chunks of
+// kBT, each placed after the grids of its bucket in earlier chunks and in
+// the same chunk before it).  cnt(j) counts the grids that reach stage j, so
+// stage j's items are the tiles of the first cnt(j) grids of that order --
+// a prefix of one list of all tiles in that order -- and the stages are laid
+// out one after another from ticket base[j].  Grids flagged at the reduce
+// step (s above smax, or a bad dt_hyp) have no items.
+__device__ __forceinline__ int stage_bucket(const GridState& st, int smax) {
+    return (st.flags & RKL_FLAG_STAGES) || st.s < 2 || st.s > smax ? 0 : st.s;
+}
+
 __global__ __launch_bounds__(kBT) void batch_schedule_kernel(const BatchGrid* __restrict__ grids,
                                                              const int* __restrict__ by_size,
                                                              const GridState* __restrict__ state, int ngrids,
                                                              int smax, int* order, int* tprefix, int2* tiles,
                                                              unsigned long long* base, PersistCtl* ctl) {
-    __shared__ int cnt[kPersistSmax + 2];        // cnt[j]: grids with s >= j
-    __shared__ int pos[kPersistSmax + 2];
-    if (threadIdx.x == 0) {
-        for (int j = 0; j <= smax + 1; ++j) { cnt[j] = 0; pos[j] = 0; }
-        for (int g = 0; g < ngrids; ++g) {
-            const GridState& st = state[g];
-            const int se = (st.flags & RKL_FLAG_STAGES) || st.s < 2 || st.s > smax ? 0 : st.s;
-            cnt[se] += 1;                          // histogram of the stage counts
-        }
-        // first position of each stage count in the order (larger s first)
+    __shared__ int cnt[kPersistSmax + 2];        // histogram, then grids with s >= j
+    __shared__ int pos[kPersistSmax + 2];        // next free place of each bucket
+    __shared__ int key[kBT];                     // buckets of the current chunk
+    __shared__ int part[kBT];                    // scan scratch
+    __shared__ int carry;
+    const int tid = threadIdx.x;
+    for (int j = tid; j <= smax + 1; j += kBT) { cnt[j] = 0; pos[j] = 0; }
+    __syncthreads();
+    for (int g = tid; g < ngrids; g += kBT) atomicAdd(&cnt[stage_bucket(state[g], smax)], 1);
+    __syncthreads();
+    if (tid == 0) {
         int acc = 0;
         for (int v = smax; v >= 0; --v) { pos[v] = acc; acc += cnt[v]; }
-        for (int k = 0; k < ngrids; ++k) {
-            const int g = by_size[k];
-            const GridState& st = state[g];
-            const int se = (st.flags & RKL_FLAG_STAGES) || st.s < 2 || st.s > smax ? 0 : st.s;
-            order[pos[se]++] = g;
-        }
         int ge = 0;
         for (int v = smax; v >= 1; --v) { ge += cnt[v]; cnt[v] = ge; }   // grids with s >= v
-        int tp = 0;
-        for (int i = 0; i < ngrids; ++i) { tprefix[i] = tp; tp += grids[order[i]].ntiles; }
-        tprefix[ngrids] = tp;
+    }
+    __syncthreads();
+    // stable scatter in chunks of kBT grids
+    for (int c = 0; c < ngrids; c += kBT) {
+        const int k = c + tid;
+        const int g = k < ngrids ? by_size[k] : -1;
+        const int v = g >= 0 ? stage_bucket(state[g], smax) : -1;
+        key[tid] = v;
+        __syncthreads();
+        if (g >= 0) {
+            int rank = 0;
+            for (int t = 0; t < tid; ++t) rank += key[t] == v;
+            order[pos[v] + rank] = g;
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (int t = 0; t < kBT; ++t)
+                if (key[t] >= 0) pos[key[t]] += 1;
+        __syncthreads();
+    }
+    // tprefix: exclusive scan of the tile counts over the order, in chunks
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int c = 0; c < ngrids; c += kBT) {
+        const int k = c + tid;
+        const int nt = k < ngrids ? grids[order[k]].ntiles : 0;
+        part[tid] = nt;
+        __syncthreads();
+        for (int off = 1; off < kBT; off <<= 1) {   // inclusive Hillis-Steele scan
+            const int add = tid >= off ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += add;
+            __syncthreads();
+        }
+        if (k < ngrids) tprefix[k] = carry + part[tid] - nt;
+        __syncthreads();
+        if (tid == kBT - 1) carry += part[tid];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        tprefix[ngrids] = carry;
         unsigned long long b = 0;
         for (int j = 1; j <= smax; ++j) { base[j] = b; b += (unsigned long long)tprefix[cnt[j]]; }
         base[0] = 0;
@@ -259,10 +297,11 @@ __global__ __launch_bounds__(kBT) void batch_schedule_kernel(const BatchGrid* __
         ctl->abort = 0u;
     }
     __syncthreads();
-    for (int i = 0; i < cnt[1]; ++i) {
+    // the tile list: each thread writes the tiles of its grids
+    for (int i = tid; i < cnt[1]; i += kBT) {
         const int g = order[i], nt = grids[g].ntiles;
         int2* w = tiles + tprefix[i];
-        for (int t = threadIdx.x; t < nt; t += kBT) w[t] = make_int2(g, t);
+        for (int t = 0; t < nt; ++t) w[t] = make_int2(g, t);
     }
 }
 

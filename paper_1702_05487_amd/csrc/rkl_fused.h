@@ -1,34 +1,41 @@
-// rkl_fused.h -- two RKL2 stages per launch (temporal fusion) for gfx950.
-// Private to librkl; included by the kernel sources only.
+// rkl_fused.h -- F consecutive RKL2 stages per launch (temporal fusion,
+// F = 2, 3 or 4) for gfx950.  Private to librkl; included by the kernel
+// sources only.
 //
-// Method: Vaidya et al. (2017), arXiv:1702.05487, Appendix A: stages j and
-// j+1 (2 <= j, j+1 < s) of
-//   Y_j = mu_j Y_{j-1} + nu_j Y_{j-2} + (1-mu_j-nu_j) Y0 + mut_j tau L(Y_{j-1})
-//         + gt_j tau M(Y0)
+// Method: Vaidya et al. (2017), arXiv:1702.05487, Appendix A: stages
+// j, ..., j+F-1 (2 <= j, j+F-1 < s) of
+//   Y_m = mu_m Y_{m-1} + nu_m Y_{m-2} + (1-mu_m-nu_m) Y0 + mut_m tau L(Y_{m-1})
+//         + gt_m tau M(Y0)
 // with L the flux divergence of Sec. 3 (face flux of Sec. 2 and Appendix B,
 // face_flux in rkl_tile.h).
 //
 // Scheme (overlapped tiles, z-march).  The workgroup's BX x BY threads own
-// one cell each of a region whose interior (BX-2) x (BY-2) is the output
-// tile.
+// one cell each of a region; a cell's distance from the region border is
+// d = min(dx, dy), dx = min(tx, BX-1-tx), dy = min(ty, BY-1-ty).
 //   Level 1 computes Y_j on the whole region, exactly as run_tile does for
 //   one stage: Y_{j-1} with a one-cell ring around the region in a
 //   three-plane LDS ring, slopes and b in two-plane rings, every face once.
-//   Level 2 computes Y_{j+1} on the interior, three planes behind level 1.
-//   Each thread hands its Y_j to level 2's LDS ring and register queue; the
-//   region's border cells supply only their slopes along the border and the
-//   faces towards the interior.  The pointwise inputs of level 2 (Y_{j-1},
-//   Y0, tau M(Y0)) and its unit vectors are the ones level 1 loaded three
-//   planes earlier, carried in register delay lines.
-// Both levels share the one barrier per plane.  HBM traffic per output cell
-// and stage pair: Y_{j-1}, Y_{j-2}, Y0, tau M(Y0) and b read once, Y_j and
-// Y_{j+1} written once; the border ring is recomputed by the neighbouring
-// tiles.  Tiles overlap, so the outputs go to buffers that the launch does
-// not read.
+//   Level l = 2..F computes Y_{j+l-1} three planes behind level l-1, on the
+//   cells with d >= l-1, from level l-1's output (valid on d >= l-2), handed
+//   over through LDS and registers.  A cell with d = l-2 supplies only its
+//   slope along the border and the faces towards the inside; the output
+//   tile is the cells with d >= F-1, of (BX-2(F-1)) x (BY-2(F-1)) cells.
+//   The pointwise inputs of level l (Y_{j+l-3}, Y0, tau M(Y0)) and its unit
+//   vectors come down from level 1's loads through register delay lines,
+//   three planes per level.
+// All levels share the one barrier per plane.  HBM traffic per output cell
+// and group of F stages: Y_{j-1}, Y_{j-2}, Y0, tau M(Y0) and b read once,
+// Y_{j+F-2} and Y_{j+F-1} (what the next launch needs) written once; the
+// border rings are recomputed by the neighbouring tiles.  Tiles overlap, so
+// the outputs go to buffers that the launch does not read.  Every level
+// performs exactly the one-stage kernel's operations, so fused and unfused
+// super-steps give the same bits.
 #pragma once
 #include "rkl_tile.h"
 
 namespace rkl {
+
+constexpr int kMaxFuse = 4;
 
 struct FusedArgs {
     const double* Yin;   // Y_{j-1}
@@ -36,38 +43,38 @@ struct FusedArgs {
     const double* Y0;
     const void* MY0;     // tau M(Y0), type R
     const void* b;       // unit vectors, type R, 3 x N
-    double* Yj;          // out: Y_j   (aliases no input)
-    double* Yj1;         // out: Y_{j+1} (aliases no input)
+    double* Ya;          // out: Y_{j+F-2} (aliases no input)
+    double* Yb;          // out: Y_{j+F-1} (aliases no input)
     int n0, n1, n2, ndim;
     int x0, y0, z0, z1;  // output tile origin and z range [z0, z1)
     double ih0, ih1, ih2;
     double scale;        // -tau (gamma-1)/rho
-    double mu1, nu1, omn1, mut1, gt1;   // stage j
-    double mu2, nu2, omn2, mut2, gt2;   // stage j+1
+    double cf[kMaxFuse][5];   // {mu, nu, 1-mu-nu, mut, gt} of stages j..j+F-1
 };
 
-template <typename R, int BX, int BY>
+template <typename R, int BX, int BY, int F>
 struct FusedLds {
-    static constexpr int PX = BX + 2, PL = (BX + 2) * (BY + 2), RL = BX * BY;
+    static constexpr int PX = BX + 2, PL = (BX + 2) * (BY + 2), RL = BX * BY, NL = F - 1;
     // level 1: region and the ring around it
     R T1[3][PL];
     R S1[2][3][PL];
     R B1[2][3][PL];
     R FX1[2][(BX + 1) * BY];
     R FY1[2][BX * (BY + 1)];
-    // level 2: region
-    R T2[3][RL];
-    R S2[2][3][RL];
-    R B2[2][3][RL];
-    R FX2[2][RL];   // face between region cells c and c+1
-    R FY2[2][RL];   // face between region cells c and c+BX
+    // levels 2..F: region
+    R T2[NL][3][RL];
+    R S2[NL][2][3][RL];
+    R B2[NL][2][3][RL];
+    R FX2[NL][2][RL];   // face between region cells c and c+1
+    R FY2[NL][2][RL];   // face between region cells c and c+BX
 };
 
-template <typename R, bool LIM, int SAT, int KM, int BX, int BY>
-__device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& fk, double tref,
-                                           FusedLds<R, BX, BY>& L) {
-    using Lds = FusedLds<R, BX, BY>;
+template <typename R, bool LIM, int SAT, int KM, int BX, int BY, int F>
+__device__ __forceinline__ void run_fused(const FusedArgs& a, const FaceK<R>& fk, double tref,
+                                          FusedLds<R, BX, BY, F>& L) {
+    using Lds = FusedLds<R, BX, BY, F>;
     constexpr int px = Lds::PX;
+    constexpr int NL = F - 1;
     const int tid = threadIdx.x;
     const int n0 = a.n0, n1 = a.n1, n2 = a.n2;
     const int plane = n0 * n1;
@@ -79,16 +86,15 @@ __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& f
     const R ih0 = R(a.ih0), ih1 = R(a.ih1), ih2 = R(a.ih2);
     const R hih0 = R(0.5 * a.ih0), hih1 = R(0.5 * a.ih1), hih2 = R(0.5 * a.ih2);
 
-    // own cell: region coordinates (tx, ty); the region starts one cell
+    // own cell: region coordinates (tx, ty); the region starts F-1 cells
     // before the output tile along x and y
     const int tx = tid % BX, ty = tid / BX;
-    const int rx = a.x0 - 1, ry = a.y0 - 1;
+    const int rx = a.x0 - (F - 1), ry = a.y0 - (F - 1);
     const int oslot = (ty + 1) * px + tx + 1;   // level-1 slot
-    const int rslot = tid;                      // level-2 slot, ty * BX + tx
+    const int rslot = tid;                      // level-l slot, ty * BX + tx
     const int oxy = wrap(ry + ty, n1) * n0 + wrap(rx + tx, n0);
-    const bool inx = tx >= 1 && tx <= BX - 2, iny = ty >= 1 && ty <= BY - 2;
-    const bool interior = inx && iny;
-    const bool store = interior && (rx + tx < n0) && (ry + ty < n1);
+    const int dx = min(tx, BX - 1 - tx), dy = min(ty, BY - 1 - ty), dd = min(dx, dy);
+    const bool store = dd >= F - 1 && (rx + tx < n0) && (ry + ty < n1);
 
     // level-1 ring cell of this thread (edges, then corners), as in run_tile
     constexpr int ne = 2 * BX + 2 * BY;
@@ -122,12 +128,14 @@ __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& f
         else { const int i = fid - BY; fdir = 1; fL = i + 1; fR = px + i + 1; fidx = i; }
     }
 
-    // Level 2 needs Y_j on planes [z0-1, z1] (x/y slopes of the planes next
-    // to the output range, for the transverse gradients of its z faces), so
-    // level 1 runs planes [l1a, l1b) = [z0-1, z1+1) and reads Y_{j-1} on
-    // [z0-3, z1+3).  Iteration K runs level-1 plane K and level-2 plane K-3.
+    // Level l computes planes [z0-(F-l), z1+(F-l)): each level needs the
+    // previous one's output one plane beyond its own range on either side
+    // (the x/y slopes of the neighbouring planes, for the transverse
+    // gradients of its z faces).  Level 1 therefore runs [l1a, l1b) and
+    // reads Y_{j-1} on [l1a-2, l1b+1]; iteration K runs level-1 plane K and
+    // level-l plane K - 3(l-1).
     const int z0 = a.z0, z1 = a.z1;
-    const int l1a = z0 - 1, l1b = z1 + 1;
+    const int l1a = z0 - (F - 1), l1b = z1 + (F - 1);
     int pz4 = wrap(l1a + 2, n2);
 
     // ---- level-1 registers, as in run_tile
@@ -141,24 +149,35 @@ __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& f
     R fzp = 0;
     double ym2 = 0.0, y0v = 0.0, q1ym2 = 0.0, q1y0 = 0.0, q2ym2 = 0.0, q2y0 = 0.0;
     R my0 = 0, q1my0 = 0, q2my0 = 0;
-    double yj = 0.0;   // Y_j of the last level-1 plane
+    double yout0 = 0.0;   // level-1 output Y_j of the last level-1 plane
 
-    // ---- delay lines from level 1 to level 2 (values of planes K-1, K-2, K-3
-    // at the start of iteration K)
-    double dy1 = 0.0, dy2 = 0.0, dy3 = 0.0;   // Y_{j-1}
-    double dz1 = 0.0, dz2 = 0.0, dz3 = 0.0;   // Y0
-    R dm1 = 0, dm2 = 0, dm3 = 0;              // tau M(Y0)
-    R db10 = 0, db11 = 0, db12 = 0, db20 = 0, db21 = 0, db22 = 0;   // b, planes K-1, K-2
-
-    // ---- level-2 registers
-    double uq0 = 0.0, uq1 = 0.0, uq2 = 0.0;   // own Y_j, planes k2, k2+1, k2+2
-    R vq0 = 0, vq1 = 0, vq2 = 0;              // same in flux precision
-    R ub00 = 0, ub01 = 0, ub02 = 0, ub10 = 0, ub11 = 0, ub12 = 0;   // own b, planes k2, k2+1
-    R us00 = 0, us01 = 0, us02 = 0, us10 = 0, us11 = 0, us12 = 0;   // own slopes, k2, k2+1
-    R gzp = 0;
+    // ---- levels 2..F (index m = l - 2)
+    double uq[NL][3];     // own input Y_{j+l-2}, planes k, k+1, k+2
+    R vq[NL][3];          // same in flux precision
+    R ub[NL][2][3];       // own b, planes k, k+1
+    R us[NL][2][3];       // own slopes, planes k, k+1
+    R gzp[NL];            // +z face flux of plane k-1
+    double yout[NL];      // output Y_{j+l-1} of the last plane
+    // delay lines into level l (values of the planes 1, 2, 3 iterations back)
+    double dY[NL][3];     // Y_{j+l-3}: level l-1's own input (level 1: Y_{j-1})
+    double dZ[NL][3];     // Y0
+    R dM[NL][3];          // tau M(Y0)
+    R dB[NL][2][3];       // b, two planes back
+    int e0[NL], e1[NL], e2[NL], ec[NL], en[NL];   // ring slots
+#pragma unroll
+    for (int m = 0; m < NL; ++m) {
+        gzp[m] = 0;
+        yout[m] = 0.0;
+        e0[m] = 0; e1[m] = 1; e2[m] = 2; ec[m] = 1; en[m] = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            uq[m][q] = 0.0; vq[m][q] = 0; dY[m][q] = 0.0; dZ[m][q] = 0.0; dM[m][q] = 0;
+            ub[m][0][q] = 0; ub[m][1][q] = 0; us[m][0][q] = 0; us[m][1][q] = 0;
+            dB[m][0][q] = 0; dB[m][1][q] = 0;
+        }
+    }
 
     int c0 = 0, c1 = 1, c2 = 2, dc = 1, dn = 0;   // level-1 ring slots
-    int e0 = 0, e1 = 1, e2 = 2, ec = 1, en = 0;   // level-2 ring slots
     int fb = 0;
 
     // level-1 prologue: ring planes l1a-2, l1a-1; prefetch l1a, l1a+1
@@ -192,18 +211,19 @@ __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& f
         oq2 = to_r<R>(yq2, tref);
         L.T1[0][oslot] = oq1;
         L.T1[1][oslot] = oq2;
-        // the level-2 ring plane below its first one is read (for slopes that
+        // the level-l ring plane below its first one is read (for slopes that
         // are never used) before it is written: give it defined values
-        L.T2[0][rslot] = R(0);
-        L.T2[1][rslot] = R(0);
-        L.T2[2][rslot] = R(0);
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            L.T2[m][0][rslot] = R(0);
+            L.T2[m][1][rslot] = R(0);
+            L.T2[m][2][rslot] = R(0);
+        }
     }
     __syncthreads();
 
-    for (int K = l1a - 2; K < z1 + 3; ++K) {
-        const int k2 = K - 3;
+    for (int K = l1a - 2; K < z1 + 3 * (F - 1); ++K) {
         const bool l1 = K < l1b;
-        const bool l2 = k2 >= z0 - 3;   // level 2 stores Y_j(k2+2) from k2+2 = z0-1 on
 
         // ============ level 1, A and B: T(K+2), b(K+1) in; slopes of K+1
         if (l1) {
@@ -253,23 +273,29 @@ __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& f
             }
         }
 
-        // ============ level 2, A and B: Y_j(k2+2) = Y_j(K-1), b(k2+1) = b(K-2)
-        // in; slopes of k2+1 (along the region border only the slopes
-        // parallel to it)
-        if (l2) {
-            uq0 = uq1; uq1 = uq2; uq2 = yj;
-            vq0 = vq1; vq1 = vq2; vq2 = to_r<R>(yj, tref);
-            L.T2[e2][rslot] = vq2;
-            L.B2[en][0][rslot] = db20; L.B2[en][1][rslot] = db21; L.B2[en][2][rslot] = db22;
-            ub00 = ub10; ub01 = ub11; ub02 = ub12;
-            ub10 = db20; ub11 = db21; ub12 = db22;
-            const R* T2 = L.T2[e1];
-            const R s0 = inx ? cell_slope<R, LIM>(T2[rslot - 1], vq1, T2[rslot + 1], hih0) : R(0);
-            const R s1 = iny ? cell_slope<R, LIM>(T2[rslot - BX], vq1, T2[rslot + BX], hih1) : R(0);
-            const R s2 = cell_slope<R, LIM>(vq0, vq1, vq2, hih2);
-            L.S2[en][0][rslot] = s0; L.S2[en][1][rslot] = s1; L.S2[en][2][rslot] = s2;
-            us00 = us10; us01 = us11; us02 = us12;
-            us10 = s0; us11 = s1; us12 = s2;
+        // ============ levels 2..F, A and B: Y_{j+l-2}(k+2) (level l-1's last
+        // output) and b(k+1) in; slopes of k+1 (where the neighbours have input)
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            const int l = m + 2;
+            const int k = K - 3 * (l - 1);
+            if (k + 2 < z0 - (F - l + 1)) continue;   // level l-1 has no output yet
+            const double yin = m == 0 ? yout0 : yout[m - 1];
+            uq[m][0] = uq[m][1]; uq[m][1] = uq[m][2]; uq[m][2] = yin;
+            vq[m][0] = vq[m][1]; vq[m][1] = vq[m][2]; vq[m][2] = to_r<R>(yin, tref);
+            L.T2[m][e2[m]][rslot] = vq[m][2];
+            L.B2[m][en[m]][0][rslot] = dB[m][1][0];
+            L.B2[m][en[m]][1][rslot] = dB[m][1][1];
+            L.B2[m][en[m]][2][rslot] = dB[m][1][2];
+            ub[m][0][0] = ub[m][1][0]; ub[m][0][1] = ub[m][1][1]; ub[m][0][2] = ub[m][1][2];
+            ub[m][1][0] = dB[m][1][0]; ub[m][1][1] = dB[m][1][1]; ub[m][1][2] = dB[m][1][2];
+            const R* T2 = L.T2[m][e1[m]];
+            const R s0 = (dx >= l - 1 && dy >= l - 2) ? cell_slope<R, LIM>(T2[rslot - 1], vq[m][1], T2[rslot + 1], hih0) : R(0);
+            const R s1 = (dy >= l - 1 && dx >= l - 2) ? cell_slope<R, LIM>(T2[rslot - BX], vq[m][1], T2[rslot + BX], hih1) : R(0);
+            const R s2 = cell_slope<R, LIM>(vq[m][0], vq[m][1], vq[m][2], hih2);
+            L.S2[m][en[m]][0][rslot] = s0; L.S2[m][en[m]][1][rslot] = s1; L.S2[m][en[m]][2][rslot] = s2;
+            us[m][0][0] = us[m][1][0]; us[m][0][1] = us[m][1][1]; us[m][0][2] = us[m][1][2];
+            us[m][1][0] = s0; us[m][1][1] = s1; us[m][1][2] = s2;
         }
 
         // ============ level 1, C: faces of plane K
@@ -301,28 +327,37 @@ __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& f
                                              ob02, ob00, ob01, ob12, ob10, ob11, fk);
         }
 
-        // ============ level 2, C: faces of plane k2 that touch the interior
-        R gzn = 0;
-        if (l2 && k2 >= z0) {
-            const R* Tk = L.T2[e0];
-            const R(*S)[Lds::RL] = L.S2[ec];
-            const R(*Bv)[Lds::RL] = L.B2[ec];
-            if (iny && tx <= BX - 2) {
-                const int r = rslot + 1;
-                L.FX2[fb][rslot] = face_flux<R, LIM, SAT, KM>(
-                    vq0, Tk[r], ih0, us01, S[1][r], us02, S[2][r],
-                    ub00, ub01, ub02, Bv[0][r], Bv[1][r], Bv[2][r], fk);
+        // ============ levels 2..F, C: faces of plane k that touch its output cells
+        R gzn[NL];
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            const int l = m + 2;
+            const int k = K - 3 * (l - 1);
+            gzn[m] = 0;
+            const int lo = z0 - (F - l), hi = z1 + (F - l);
+            if (k + 2 < z0 - (F - l + 1)) continue;
+            if (k >= lo && k < hi) {
+                const R* Tk = L.T2[m][e0[m]];
+                const R(*S)[Lds::RL] = L.S2[m][ec[m]];
+                const R(*Bv)[Lds::RL] = L.B2[m][ec[m]];
+                if (dy >= l - 1 && tx >= l - 2 && tx <= BX - l) {
+                    const int r = rslot + 1;
+                    L.FX2[m][fb][rslot] = face_flux<R, LIM, SAT, KM>(
+                        vq[m][0], Tk[r], ih0, us[m][0][1], S[1][r], us[m][0][2], S[2][r],
+                        ub[m][0][0], ub[m][0][1], ub[m][0][2], Bv[0][r], Bv[1][r], Bv[2][r], fk);
+                }
+                if (dx >= l - 1 && ty >= l - 2 && ty <= BY - l) {
+                    const int u = rslot + BX;
+                    L.FY2[m][fb][rslot] = face_flux<R, LIM, SAT, KM>(
+                        vq[m][0], Tk[u], ih1, us[m][0][0], S[0][u], us[m][0][2], S[2][u],
+                        ub[m][0][1], ub[m][0][0], ub[m][0][2], Bv[1][u], Bv[0][u], Bv[2][u], fk);
+                }
             }
-            if (inx && ty <= BY - 2) {
-                const int u = rslot + BX;
-                L.FY2[fb][rslot] = face_flux<R, LIM, SAT, KM>(
-                    vq0, Tk[u], ih1, us00, S[0][u], us02, S[2][u],
-                    ub01, ub00, ub02, Bv[1][u], Bv[0][u], Bv[2][u], fk);
+            if (dd >= l - 1 && k >= lo - 1 && k < hi) {
+                gzn[m] = face_flux<R, LIM, SAT, KM>(vq[m][0], vq[m][1], ih2, us[m][0][0], us[m][1][0], us[m][0][1],
+                                                    us[m][1][1], ub[m][0][2], ub[m][0][0], ub[m][0][1], ub[m][1][2],
+                                                    ub[m][1][0], ub[m][1][1], fk);
             }
-        }
-        if (l2 && interior && k2 >= z0 - 1) {
-            gzn = face_flux<R, LIM, SAT, KM>(vq0, vq1, ih2, us00, us10, us01, us11,
-                                             ub02, ub00, ub01, ub12, ub10, ub11, fk);
         }
         __syncthreads();
 
@@ -335,38 +370,65 @@ __device__ __forceinline__ void run_fused2(const FusedArgs& a, const FaceK<R>& f
             div = fma(FY[(ty + 1) * BX + tx] - FY[ty * BX + tx], ih1, div);
             div = fma(fzn - fzp, ih2, div);
             const double tl = a.scale * (double)div;
-            yj = stage_combine(a.mu1, a.nu1, a.omn1, a.mut1, a.gt1, yq0, ym2, y0v, tl, (double)my0);
-            if (store && K >= z0 && K < z1) a.Yj[(size_t)K * plane + oxy] = yj;
+            const double* c = a.cf[0];
+            yout0 = stage_combine(c[0], c[1], c[2], c[3], c[4], yq0, ym2, y0v, tl, (double)my0);
+            if (F == 2 && store && K >= z0 && K < z1) a.Ya[(size_t)K * plane + oxy] = yout0;
         }
         fzp = fzn;
 
-        // ============ level 2, D: Y_{j+1} of plane k2 on the interior
-        if (l2 && k2 >= z0 && store) {
-            const R* FX = L.FX2[fb];
-            const R* FY = L.FY2[fb];
-            R div = (FX[rslot] - FX[rslot - 1]) * ih0;
-            div = fma(FY[rslot] - FY[rslot - BX], ih1, div);
-            div = fma(gzn - gzp, ih2, div);
-            const double tl = a.scale * (double)div;
-            a.Yj1[(size_t)k2 * plane + oxy] =
-                stage_combine(a.mu2, a.nu2, a.omn2, a.mut2, a.gt2, uq0, dy3, dz3, tl, (double)dm3);
+        // ============ levels 2..F, D: Y_{j+l-1} of plane k on the cells with d >= l-1
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            const int l = m + 2;
+            const int k = K - 3 * (l - 1);
+            const int lo = z0 - (F - l), hi = z1 + (F - l);
+            if (k + 2 < z0 - (F - l + 1)) continue;
+            if (k >= lo && k < hi && dd >= l - 1) {
+                const R* FX = L.FX2[m][fb];
+                const R* FY = L.FY2[m][fb];
+                R div = (FX[rslot] - FX[rslot - 1]) * ih0;
+                div = fma(FY[rslot] - FY[rslot - BX], ih1, div);
+                div = fma(gzn[m] - gzp[m], ih2, div);
+                const double tl = a.scale * (double)div;
+                const double* c = a.cf[l - 1];
+                yout[m] = stage_combine(c[0], c[1], c[2], c[3], c[4], uq[m][0], dY[m][2], dZ[m][2], tl,
+                                        (double)dM[m][2]);
+                if (store && k >= z0 && k < z1) {
+                    if (l == F - 1) a.Ya[(size_t)k * plane + oxy] = yout[m];
+                    if (l == F) a.Yb[(size_t)k * plane + oxy] = yout[m];
+                }
+            }
+            gzp[m] = gzn[m];
         }
-        gzp = gzn;
 
-        // delay lines: push plane K
-        dy3 = dy2; dy2 = dy1; dy1 = yq0;
-        dz3 = dz2; dz2 = dz1; dz1 = y0v;
-        dm3 = dm2; dm2 = dm1; dm1 = my0;
-        db20 = db10; db21 = db11; db22 = db12;
-        db10 = ob00; db11 = ob01; db12 = ob02;
+        // delay lines: push this iteration's values, highest level first (a
+        // level's source is the line of the level before it)
+#pragma unroll
+        for (int m = NL - 1; m >= 0; --m) {
+            const double srcY = m == 0 ? yq0 : uq[m - 1][0];
+            const double srcZ = m == 0 ? y0v : dZ[m - 1][2];
+            const R srcM = m == 0 ? my0 : dM[m - 1][2];
+            const R sb0 = m == 0 ? ob00 : ub[m - 1][0][0];
+            const R sb1 = m == 0 ? ob01 : ub[m - 1][0][1];
+            const R sb2 = m == 0 ? ob02 : ub[m - 1][0][2];
+            dY[m][2] = dY[m][1]; dY[m][1] = dY[m][0]; dY[m][0] = srcY;
+            dZ[m][2] = dZ[m][1]; dZ[m][1] = dZ[m][0]; dZ[m][0] = srcZ;
+            dM[m][2] = dM[m][1]; dM[m][1] = dM[m][0]; dM[m][0] = srcM;
+            dB[m][1][0] = dB[m][0][0]; dB[m][1][1] = dB[m][0][1]; dB[m][1][2] = dB[m][0][2];
+            dB[m][0][0] = sb0; dB[m][0][1] = sb1; dB[m][0][2] = sb2;
+        }
 
         if (l1) {
             const int t = c0; c0 = c1; c1 = c2; c2 = t;
             const int d = dc; dc = dn; dn = d;
         }
-        if (l2) {
-            const int t = e0; e0 = e1; e1 = e2; e2 = t;
-            const int d = ec; ec = en; en = d;
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+            const int l = m + 2;
+            const int k = K - 3 * (l - 1);
+            if (k + 2 < z0 - (F - l + 1)) continue;
+            const int t = e0[m]; e0[m] = e1[m]; e1[m] = e2[m]; e2[m] = t;
+            const int d = ec[m]; ec[m] = en[m]; en[m] = d;
         }
         fb ^= 1;
     }

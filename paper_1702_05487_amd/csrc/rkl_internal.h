@@ -145,10 +145,11 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
                         const double* coef, hipStream_t st, double sub_scale = 0.0,
                         const Route* route = nullptr);
-// stages j and j+1 (2 <= j, j+1 < s) in one launch, RKL_MIXED and 3-D grids
-// only; Yj and Yj1 must alias none of Yin, Ym2, Y0
-hipError_t launch_fused2(Variant v, const GridConst& gc, int stage, const double* Yin, const double* Ym2,
-                         const double* Y0, const void* MY0, double* Yj, double* Yj1, const void* b,
-                         const GridState* state, const double* coef, hipStream_t st);
+// stages j..j+F-1 (F = v.fuse in 2..4, 2 <= j, j+F-1 < s) in one launch,
+// RKL_MIXED and periodic 3-D grids only; Ya receives Y_{j+F-2}, Yb Y_{j+F-1};
+// they must alias none of Yin, Ym2, Y0
+hipError_t launch_fused(Variant v, const GridConst& gc, int stage, const double* Yin, const double* Ym2,
+                        const double* Y0, const void* MY0, double* Ya, double* Yb, const void* b,
+                        const GridState* state, const double* coef, hipStream_t st);
 
 }  // namespace rkl

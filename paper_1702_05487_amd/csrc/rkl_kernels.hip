@@ -9,12 +9,14 @@ namespace rkl {
 
 // ------------------------------------------------------------ variants ----
 // (bx, by) are compile-time tile shapes; bz is the z-chunk length per block;
-// fuse is the number of stages per launch (2: rkl_fused.hip, where (bx, by)
-// is the region of a workgroup and (bx-2, by-2) its output tile).
+// fuse is the number of stages per launch (F = 2..4: rkl_fused.hip, where
+// (bx, by) is the region of a workgroup and (bx-2(F-1), by-2(F-1)) its
+// output tile).
 static const Variant kVariants[] = {
     {32, 8, 32, 1}, {32, 8, 64, 1}, {64, 4, 32, 1}, {64, 4, 64, 1}, {16, 16, 32, 1}, {16, 16, 64, 1},
     {32, 8, 16, 1}, {64, 4, 16, 1},
     {16, 16, 32, 2}, {16, 16, 64, 2}, {32, 8, 32, 2}, {32, 8, 64, 2},
+    {16, 16, 32, 3}, {16, 16, 64, 3}, {16, 16, 32, 4}, {16, 16, 64, 4},
 };
 int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 Variant variant_get(int v) { return kVariants[v]; }

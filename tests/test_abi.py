@@ -78,11 +78,12 @@ def test_variant_table():
     fuses = set()
     for v in range(n):
         bx, by, bz, fuse = rkl.rkl_variant_info(v)
-        assert bx * by <= 1024 and bz >= 1 and fuse in (1, 2)
+        assert bx * by <= 1024 and bz >= 1 and fuse in (1, 2, 3, 4)
         fuses.add(fuse)
-        if fuse == 2:
-            assert bx >= 3 and by >= 3   # the output tile is (bx-2) x (by-2)
-    assert fuses == {1, 2}
+        if fuse >= 2:
+            # the output tile is (bx-2(F-1)) x (by-2(F-1))
+            assert bx > 2 * (fuse - 1) and by > 2 * (fuse - 1)
+    assert fuses == {1, 2, 3, 4}
     with pytest.raises(rkl.RklError):
         rkl.rkl_variant_info(n)
 
@@ -131,7 +132,7 @@ int main(void) {
     int n = rkl_variant_count(), tx, ty, tz, fuse, fused = 0;
     for (int v = 0; v < n; ++v) {
         if (rkl_variant_info(v, &tx, &ty, &tz, &fuse) != RKL_OK) return 4;
-        fused += fuse == 2;
+        fused += fuse >= 2;
     }
     if (rkl_variant_info(n, &tx, &ty, &tz, &fuse) != RKL_EINVAL) return 5;
     if (rkl_destroy(NULL) != RKL_OK) return 6;

@@ -91,8 +91,8 @@ def test_two_stage_launches(tmp_root):
     seq = [(COPY, GIB),
            ("void rkl::finalize_kernel(double const*, int, rkl::GridConst, ...)", 1024.0),
            ("void rkl::stage_kernel<float, true, 1, 1, 64, 4, true>(rkl::StageLaunch)", 5000.0 * 1024),   # stage 1
-           ("void rkl::fused2_kernel<true, 16, 16, 32>(rkl::FusedLaunch)", 600.0 * 1024),
-           ("void rkl::fused2_kernel<true, 16, 16, 32>(rkl::FusedLaunch)", 800.0 * 1024),
+           ("void rkl::fused_kernel<true, 1, 1, 16, 16, 2>(rkl::FusedLaunch)", 600.0 * 1024),
+           ("void rkl::fused_kernel<true, 1, 1, 16, 16, 2>(rkl::FusedLaunch)", 800.0 * 1024),
            ("void rkl::stage_kernel<float, true, 1, 1, 64, 4, true>(rkl::StageLaunch)", 5000.0 * 1024)]  # last stage
     r, w = tmp_root / "read.csv", tmp_root / "write.csv"
     write_reads(r, seq)

@@ -1,5 +1,5 @@
-"""Two-stage (temporally fused) kernel variants vs the FP64 oracle, through
-the C ABI, on RKL_MIXED plans of 3-D grids.
+"""Temporally fused kernel variants (F = 2, 3 or 4 stages per launch) vs the
+FP64 oracle, through the C ABI, on RKL_MIXED plans of 3-D grids.
 
 Bars: super-step rel-L1 <= 1e-5 against the oracle (the mixed-precision
 tolerance), identical stage counts; against the one-stage mixed path
@@ -16,7 +16,8 @@ from paper_1702_05487_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-FUSED = range(8, 12)   # variants with two stages per launch (checked in the tests)
+FUSED = range(8, 16)   # variants with several stages per launch (checked in the tests)
+DEPTH = {8: 2, 9: 2, 10: 2, 11: 2, 12: 3, 13: 3, 14: 4, 15: 4}
 
 
 @pytest.fixture(scope="module")
@@ -82,7 +83,8 @@ def run_case(torch, name, variant, steps, ratio, with_oracle=True):
 
 def test_fused_variant_table(torch_cuda):
     from paper_1702_05487_amd import rkl
-    assert [v for v in range(rkl.rkl_variant_count()) if rkl.rkl_variant_info(v)[3] == 2] == list(FUSED)
+    assert [v for v in range(rkl.rkl_variant_count()) if rkl.rkl_variant_info(v)[3] >= 2] == list(FUSED)
+    assert {v: rkl.rkl_variant_info(v)[3] for v in FUSED} == DEPTH
 
 
 @pytest.mark.parametrize("variant", FUSED)
@@ -99,21 +101,23 @@ def test_fused_matches_oracle(torch_cuda, variant, name, steps, s):
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("s", [2, 3, 4, 5, 6])
-def test_fused_small_stage_counts(torch_cuda, s):
-    """s = 2, 3: no stage pair fits before the last stage; s = 4, 6: pairs
-    only; s = 5: one pair and one single stage before the last."""
-    print("fused small s", s, flush=True)
-    g, o, T0, s_run = run_case(torch_cuda, "spitzer_mc_sat", 8, 1, inputs.midpoint_ratio(s))
+@pytest.mark.parametrize("variant", [8, 12, 14])
+@pytest.mark.parametrize("s", [2, 3, 4, 5, 6, 7, 8, 9])
+def test_fused_small_stage_counts(torch_cuda, variant, s):
+    """Stages 2..s-1 go in groups of F, the last stage and a shorter
+    remainder one stage per launch: every split of s = 2..9 for F = 2, 3, 4
+    (s = 2, 3 have no group for F = 2; s <= F has none at all)."""
+    print("fused small s", variant, s, flush=True)
+    g, o, T0, s_run = run_case(torch_cuda, "spitzer_mc_sat", variant, 1, inputs.midpoint_ratio(s))
     assert s_run == s
     assert rel_l1(g, o) <= 1e-5
 
 
 @pytest.mark.parametrize("name,s", [("spitzer_mc", 16), ("zchunks_const", 11), ("power_law_mean", 7)])
 def test_fused_equals_one_stage_path(torch_cuda, name, s):
-    """Level 2 of the fused kernel performs the one-stage kernel's operations
-    on the same values in the same order (no automatic contraction), so every
-    variant, fused or not, gives the same bits."""
+    """Every level of the fused kernels performs the one-stage kernel's
+    operations on the same values in the same order (no automatic
+    contraction), so every variant, fused or not, gives the same bits."""
     print("fused vs one-stage", name, s, flush=True)
     ratio = inputs.midpoint_ratio(s)
     one, _, T0, _ = run_case(torch_cuda, name, 0, 1, ratio, with_oracle=False)
@@ -165,9 +169,13 @@ def test_fused_768_sampled_full_size(torch_cuda, precision):
     """768^3 tangled field, kappa = T^2.5, kappa_perp = 1e-3, MC, saturation,
     s = 32: one full-size super-step against the oracle at sampled cells
     (periodic windows of half-width s+1, which the stencil cannot cross in
-    s stages).  Mixed: every two-stage variant and the one-stage 32x8 and
-    64x4x64 variants (the autotuner's pick), max |diff| <= 4e-5; FP64: the
-    one-stage 32x8x64 variant it picks there, max |diff| <= 1e-12 |T|."""
+    s stages; 12 cells, the corners of the box among them).  Mixed: every
+    fused variant and the one-stage 32x8 and 64x4x64 variants (the
+    autotuner's pick), against the oracle fed the FP32 unit vectors: max
+    |diff| <= 1e-6 (T ~ 1: FP32 flux arithmetic on differences of
+    temperatures offset to their mean leaves ~1e-7) and rel-L1 of the change
+    <= 1e-5; FP64: the one-stage 32x8x64 variant it picks there,
+    max |diff| <= 1e-12 |T|."""
     torch = torch_cuda
     from paper_1702_05487_amd import rkl
     w = inputs.fused_768(fields=False)
@@ -179,7 +187,8 @@ def test_fused_768_sampled_full_size(torch_cuda, precision):
     plan = rkl.Plan([lib_desc(w.n, w.h, 3, w.params)], precision=precision)
     dt = w.ratio * plan.dt_par(T0)
     rng = np.random.default_rng(11)
-    centers = [tuple(int(v) for v in rng.integers(0, 768, 3)) for _ in range(3)] + [(0, 0, 0), (767, 5, 767)]
+    centers = [tuple(int(v) for v in rng.integers(0, 768, 3)) for _ in range(10)] + [(0, 0, 0), (767, 5, 767)]
+    oracle.set_threads(min(16, len(__import__("os").sched_getaffinity(0))))
     s_target = 32                       # the workload's dt_hyp is set for s = 32
     r = s_target + 1
     ref = []
@@ -187,6 +196,7 @@ def test_fused_768_sampled_full_size(torch_cuda, precision):
         win = oracle.Grid(n=(2 * r + 1,) * 3, h=tuple(w.h), ndim=3, **w.params)
         ref.append(oracle.rkl2_fixed(win, _window_t(torch, T0, c, r), _window_t(torch, b, c, r), s_target, dt)[r, r, r])
     ref = np.array(ref)
+    oracle.set_threads(1)
     print("oracle samples done", flush=True)
     idx = tuple(torch.tensor(np.array(centers).T, device="cuda:0"))
     t0 = T0[idx].cpu().numpy()
@@ -199,8 +209,8 @@ def test_fused_768_sampled_full_size(torch_cuda, precision):
         print("  %s variant %d: max |diff| %.3e, change rel-L1 %.3e" % (precision, v, np.abs(got - ref).max(),
                                                                       rel_l1(got - t0, ref - t0)), flush=True)
         if precision == "mixed":
-            assert np.abs(got - ref).max() <= 4e-5
-            assert rel_l1(got - t0, ref - t0) <= 1e-2
+            assert np.abs(got - ref).max() <= 1e-6
+            assert rel_l1(got - t0, ref - t0) <= 1e-5
         else:
             assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
             assert rel_l1(got - t0, ref - t0) <= 1e-9
