@@ -35,13 +35,16 @@ class _CGrid(ctypes.Structure):
         ("gamma", ctypes.c_double),
         ("cp", ctypes.c_double),
         ("boundary", ctypes.c_int * 3),
+        ("ghost", (ctypes.POINTER(ctypes.c_double) * 2) * 3),
     ]
 
 
 @dataclass
 class Grid:
     """Grid + conduction parameters (same meaning as in rkl_oracle.c);
-    boundary[d] = 0 periodic, 1 outflow."""
+    boundary[d] = 0 periodic, 1 outflow, 2 fixed.  ghosts[d] (fixed axes):
+    (low, high) layers of ghost temperatures, each of shape (n_b+2, n_a+2)
+    for the other two axes a < b (see ghost_shape)."""
     n: tuple                      # (n0, n1, n2), axis 0 fastest
     h: tuple = (1.0, 1.0, 1.0)
     ndim: int = 3
@@ -55,6 +58,7 @@ class Grid:
     gamma: float = 2.0
     cp: float = 0.5
     boundary: tuple = (0, 0, 0)
+    ghosts: tuple = (None, None, None)
     _c: _CGrid = field(default=None, repr=False, compare=False)
 
     @property
@@ -76,9 +80,28 @@ class Grid:
         g.rho = float(self.rho)
         g.gamma = float(self.gamma)
         g.cp = float(self.cp)
+        keep = []
         for d in range(3):
             g.boundary[d] = int(self.boundary[d])
+            if self.boundary[d] != 2:
+                continue
+            if self.ghosts is None or self.ghosts[d] is None:
+                raise ValueError("axis %d is fixed but has no ghost layers" % d)
+            for side in range(2):
+                a = np.ascontiguousarray(self.ghosts[d][side], dtype=np.float64)
+                if a.shape != ghost_shape(self.n, d):
+                    raise ValueError("ghost layer of axis %d has shape %s, not %s" % (d, a.shape, ghost_shape(self.n, d)))
+                keep.append(a)
+                g.ghost[d][side] = _ptr(a)
+        g._keep = keep          # the layers live as long as the structure
         return g
+
+
+def ghost_shape(n, d: int):
+    """shape of one ghost layer of axis d of a grid of n = (n0, n1, n2)
+    cells: (n_b + 2, n_a + 2), a < b the other two axes"""
+    a, b = [e for e in range(3) if e != d]
+    return (n[b] + 2, n[a] + 2)
 
 
 def build(force: bool = False) -> str:

@@ -38,9 +38,10 @@
  *   blend either way; c_iso = sqrt(T)
  *   (p = rho T in code units); the stage operator is evaluated on each
  *   stage's own temperature and tau*M(Y0) is computed once and reused;
- *   each axis is periodic or outflow (ghost cells repeat the edge cell's T
- *   and b, as in the exact-solution or outflow ghosts the paper's tests use
- *   at non-periodic edges).
+ *   each axis is periodic, outflow (ghost cells repeat the edge cell's T
+ *   and b) or fixed (ghost temperatures given by the caller and held over
+ *   the super-step, as the Gaussian test of Sec. 4.1.1 takes its edge values
+ *   from the exact solution; b repeats the edge cell's).
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared (no fast-math), so every
  * a*b+c rounds twice, exactly as written.
@@ -87,7 +88,17 @@ typedef struct {
     double gamma;       /* ratio of specific heats */
     double cp;          /* parabolic Courant number, <= 1/2 */
     int boundary[3];    /* per axis: 0 periodic, 1 outflow (the cells beyond
-                           an edge repeat the edge cell: zero-gradient ghosts) */
+                           an edge repeat the edge cell: zero-gradient ghosts),
+                           2 fixed (ghost temperatures from ghost[d]) */
+    /* fixed axis d: ghost[d][0] and ghost[d][1] are the temperatures beyond
+     * the low and the high edge, one layer each, of (n_b + 2) x (n_a + 2)
+     * values (a < b the other two axes), index (j_b + 1) (n_a + 2) + j_a + 1
+     * for transverse position (j_a, j_b), j in [-1, n].  A position beyond
+     * the edges of several fixed axes takes the layer of the lowest of them;
+     * a transverse index is wrapped on a periodic axis, clamped to [0, n-1]
+     * on an outflow axis and to [-1, n] on a fixed one; every position
+     * beyond an edge (however far) takes that edge's layer. */
+    const double *ghost[3][2];
 } orc_grid;
 
 static long ncell(const orc_grid *g) { return (long)g->n[0] * g->n[1] * g->n[2]; }
@@ -108,11 +119,40 @@ static long cell_index(const orc_grid *g, const int c[3])
     return ((long)w[2] * g->n[1] + w[1]) * g->n[0] + w[0];
 }
 
+/* temperature at position c: a ghost value where c lies beyond an edge of a
+ * fixed axis, else the (wrapped or clamped) cell's */
+static double temp_at(const orc_grid *g, const double *T, const int c[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        if (g->boundary[d] != 2 || (c[d] >= 0 && c[d] < g->n[d])) continue;
+        const int side = c[d] >= g->n[d];
+        int t[2], k = 0;
+        for (int e = 0; e < 3; ++e) {
+            if (e == d) continue;
+            const int n = g->n[e];
+            int v = c[e];
+            if (g->boundary[e] == 0) {
+                v %= n;
+                if (v < 0) v += n;
+            } else {
+                const int lo = g->boundary[e] == 2 ? -1 : 0, hi = g->boundary[e] == 2 ? n : n - 1;
+                v = v < lo ? lo : (v > hi ? hi : v);
+            }
+            t[k++] = v;
+        }
+        int na = 0;
+        for (int e = 0; e < 3; ++e)
+            if (e != d) { na = g->n[e]; break; }
+        return g->ghost[d][side][(long)(t[1] + 1) * (na + 2) + (t[0] + 1)];
+    }
+    return T[cell_index(g, c)];
+}
+
 static double value_at(const orc_grid *g, const double *f, const int c[3], int d, int shift)
 {
     int q[3] = {c[0], c[1], c[2]};
     q[d] += shift;
-    return f[cell_index(g, q)];
+    return temp_at(g, f, q);
 }
 
 /* Parallel conductivity kappa0 * T^kappa_exp with T clipped at zero. */
@@ -146,7 +186,7 @@ static double face_flux(const orc_grid *g, const double *T, const double *b,
     int r[3] = {c[0], c[1], c[2]};
     r[d] += 1;
     const long iL = cell_index(g, c), iR = cell_index(g, r);
-    const double TL = T[iL], TR = T[iR];
+    const double TL = temp_at(g, T, c), TR = temp_at(g, T, r);
 
     /* temperature and conductivities at the face */
     const double Tf = 0.5 * (TL + TR);
