@@ -62,10 +62,13 @@ enum { RKL_LIM_NONE = 0, RKL_LIM_MC = 1 };
  * temperature of the upwind cell, the one the classical face flux leaves
  * (the upwind treatment of the saturated term that Sec. 3 names) */
 enum { RKL_SAT_NONE = 0, RKL_SAT_CENTRAL = 1, RKL_SAT_UPWIND = 2 };
-/* per-axis boundary: periodic, or outflow (the cells beyond an edge repeat
- * the edge cell's T and b at every stage: zero-gradient ghost cells, the
- * non-periodic edges of the paper's tests) */
-enum { RKL_BC_PERIODIC = 0, RKL_BC_OUTFLOW = 1 };
+/* per-axis boundary: periodic; outflow (the cells beyond an edge repeat
+ * the edge cell's T and b at every stage: zero-gradient ghost cells); or
+ * fixed (Dirichlet: the temperatures beyond the edges are given by the
+ * caller, see rkl_set_ghosts, and b repeats the edge cell's), the
+ * non-periodic edges of the paper's tests (Sec. 4.1.1 takes the Gaussian
+ * test's edge values from the exact solution). */
+enum { RKL_BC_PERIODIC = 0, RKL_BC_OUTFLOW = 1, RKL_BC_FIXED = 2 };
 
 /* flag bits reported by rkl_query */
 enum {
@@ -92,7 +95,8 @@ typedef struct {
     double gamma;         /* ratio of specific heats, > 1 */
     double cp;            /* parabolic Courant number of Eq. dt_exp, in (0, 1/2] */
     int32_t boundary[3];  /* per axis: RKL_BC_PERIODIC (0, the default of a
-                             zeroed descriptor) or RKL_BC_OUTFLOW */
+                             zeroed descriptor), RKL_BC_OUTFLOW or, for
+                             d < ndim, RKL_BC_FIXED */
 } rkl_grid_desc;
 
 typedef struct {
@@ -129,6 +133,31 @@ rkl_status rkl_destroy(rkl_plan_t plan);
 /* Cells in the packed layout before grid `grid` (b of that grid starts at
  * 3 * offset).  Returns -1 for a bad plan or index. */
 int64_t rkl_grid_offset(rkl_plan_t plan, int32_t grid);
+
+/*
+ * rkl_set_ghosts: the ghost temperatures of a fixed (Dirichlet) axis of one
+ * grid, beyond its low edge (lo) and its high edge (hi) -- the paper's
+ * Gaussian test (Sec. 4.1.1) takes these from the exact solution.  Each is
+ * a device array of (n_b + 2) x (n_a + 2) doubles, a < b the grid's other
+ * two axes: the value for transverse position (j_a, j_b), j in [-1, n], at
+ * index (j_b + 1) * (n_a + 2) + (j_a + 1).  A position beyond the edges of
+ * several fixed axes takes the layer of the lowest of them; a transverse
+ * index is wrapped on a periodic axis, clamped to [0, n-1] on an outflow
+ * axis and to [-1, n] on a fixed one; positions further beyond an edge take
+ * that edge's layer.  The values hold for every stage of a super-step (for
+ * second order in time with time-dependent edge values, give them at the
+ * super-step's midpoint).  The plan keeps the pointers, not the values: the
+ * caller owns the arrays, keeps them alive while the plan may use them and
+ * may rewrite them between calls (stream order).  Used by rkl_superstep (both
+ * schemes), rkl_superstep_async, rkl_flux_div, rkl_subcycle and rkl_aag,
+ * which return RKL_EINVAL while a fixed axis has no layers; the batched entry
+ * points and rkl_superstep_noalloc do not take fixed axes (RKL_EINVAL), and
+ * neither do the fused variants (periodic grids only).  dt_par (Eq. dt_exp)
+ * is taken over the grid's own cells.
+ * Errors: RKL_EINVAL (bad plan, grid or axis, an axis that is not fixed, a
+ * NULL pointer).
+ */
+rkl_status rkl_set_ghosts(rkl_plan_t plan, int32_t grid, int32_t axis, const double *lo, const double *hi);
 
 /*
  * rkl_flux_div: out[i] = (gamma-1)/rho * ( -div F_c(T) )_i for one grid

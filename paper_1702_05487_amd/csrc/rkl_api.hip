@@ -124,12 +124,18 @@ bool rkl::validate(const rkl_grid_desc& g, std::string& why) {
     if (!(g.rho > 0.0) || !std::isfinite(g.rho)) { why = "rho must be finite and > 0"; return false; }
     if (!(g.gamma > 1.0) || !std::isfinite(g.gamma)) { why = "gamma must be finite and > 1"; return false; }
     if (!(g.cp > 0.0 && g.cp <= 0.5)) { why = "cp must be in (0, 1/2]"; return false; }
-    for (int d = 0; d < 3; ++d)
-        if (g.boundary[d] != RKL_BC_PERIODIC && g.boundary[d] != RKL_BC_OUTFLOW) {
-            snprintf(buf, sizeof buf, "boundary[%d] must be RKL_BC_PERIODIC or RKL_BC_OUTFLOW", d);
+    for (int d = 0; d < 3; ++d) {
+        if (g.boundary[d] != RKL_BC_PERIODIC && g.boundary[d] != RKL_BC_OUTFLOW && g.boundary[d] != RKL_BC_FIXED) {
+            snprintf(buf, sizeof buf, "boundary[%d] must be RKL_BC_PERIODIC, RKL_BC_OUTFLOW or RKL_BC_FIXED", d);
             why = buf;
             return false;
         }
+        if (g.boundary[d] == RKL_BC_FIXED && d >= g.ndim) {
+            snprintf(buf, sizeof buf, "boundary[%d] = RKL_BC_FIXED needs ndim > %d", d, d);
+            why = buf;
+            return false;
+        }
+    }
     return true;
 }
 
@@ -151,6 +157,9 @@ GridConst rkl::make_const(const rkl_grid_desc& g, int scheme) {
     c.saturation = g.saturation;
     c.scheme = scheme;
     c.bc = (g.boundary[0] ? 1 : 0) | (g.boundary[1] ? 2 : 0) | (g.boundary[2] ? 4 : 0);
+    c.fixed = 0;
+    for (int d = 0; d < 3; ++d) c.fixed |= g.boundary[d] == RKL_BC_FIXED ? 1 << d : 0;
+    for (int i = 0; i < 6; ++i) c.gh[i] = nullptr;
     c.fac = (g.gamma - 1.0) / g.rho;
     c.cp = g.cp;
     double s = 0.0;
@@ -239,6 +248,23 @@ static rkl_status select_batch_mode(rkl_plan_s* p, int mode) {
     return st;
 }
 
+// a stencil call on grid g: every fixed axis needs its ghost layers
+static rkl_status check_ghosts(rkl_plan_t p, int32_t g) {
+    const GridConst& c = p->gc[g];
+    for (int d = 0; d < 3; ++d)
+        if ((c.fixed & (1 << d)) && (!c.gh[2 * d] || !c.gh[2 * d + 1]))
+            return fail(RKL_EINVAL, "grid " + std::to_string(g) + ": fixed axis " + std::to_string(d) +
+                                        " has no ghost layers (rkl_set_ghosts)");
+    return RKL_OK;
+}
+
+// the batched kernels and the fused variants have no fixed-axis ghosts
+static rkl_status check_no_fixed(rkl_plan_t p, const char* what) {
+    for (int g = 0; g < p->ngrids; ++g)
+        if (p->gc[g].fixed) return fail(RKL_EINVAL, std::string(what) + " does not take RKL_BC_FIXED axes");
+    return RKL_OK;
+}
+
 extern "C" {
 
 const char* rkl_last_error(void) { return g_err.c_str(); }
@@ -269,6 +295,7 @@ rkl_status rkl_set_batch_policy(rkl_plan_t p, int32_t policy) {
 rkl_status rkl_autotune_batched(rkl_plan_t p, const double* T, const void* b, const double* dt_hyp,
                                 int32_t reps, int32_t* best_policy, double* best_ms, void* stream) {
     if (rkl_status st = check_plan(p)) return st;
+    if (rkl_status st = check_no_fixed(p, "the batched path")) return st;
     if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
     if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     if (reps < 1 || reps > 1000) return fail(RKL_EINVAL, "reps must be in [1, 1000]");
@@ -460,6 +487,17 @@ int64_t rkl_grid_offset(rkl_plan_t p, int32_t g) {
     return p->off[g];
 }
 
+rkl_status rkl_set_ghosts(rkl_plan_t p, int32_t g, int32_t axis, const double* lo, const double* hi) {
+    if (rkl_status st = check_plan(p)) return st;
+    if (g < 0 || g >= p->ngrids) return fail(RKL_EINVAL, "grid index out of range");
+    if (axis < 0 || axis > 2) return fail(RKL_EINVAL, "axis must be 0, 1 or 2");
+    if (!(p->gc[g].fixed & (1 << axis))) return fail(RKL_EINVAL, "axis is not RKL_BC_FIXED");
+    if (!lo || !hi) return fail(RKL_EINVAL, "NULL ghost layer");
+    p->gc[g].gh[2 * axis] = lo;
+    p->gc[g].gh[2 * axis + 1] = hi;
+    return RKL_OK;
+}
+
 rkl_status rkl_set_variant(rkl_plan_t p, int32_t v) {
     if (rkl_status st = check_plan(p)) return st;
     if (v < 0 || v >= variant_count()) return fail(RKL_EINVAL, "variant out of range");
@@ -486,6 +524,7 @@ static rkl_status reduce_and_finalize(rkl_plan_t p, int32_t g, const double* T, 
 rkl_status rkl_flux_div(rkl_plan_t p, int32_t g, const double* T, const void* b, double* out, void* stream) {
     rkl_status st = check_grid(p, g);
     if (st != RKL_OK) return st;
+    if ((st = check_ghosts(p, g)) != RKL_OK) return st;
     if (!T || !b || !out) return fail(RKL_EINVAL, "NULL field pointer");
     if (out == T || (const void*)out == b) return fail(RKL_EINVAL, "out must not alias T or b");
     hipStream_t s = (hipStream_t)stream;
@@ -515,6 +554,7 @@ rkl_status rkl_superstep(rkl_plan_t p, int32_t g, double* T, const void* b, doub
                          void* stream) {
     rkl_status st = check_grid(p, g);
     if (st != RKL_OK) return st;
+    if ((st = check_ghosts(p, g)) != RKL_OK) return st;
     if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
     if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
@@ -600,6 +640,7 @@ rkl_status rkl_superstep_async(rkl_plan_t p, int32_t g, double* T, const void* b
                                int32_t s_cap, int32_t* s_out, void* stream) {
     rkl_status st = check_grid(p, g);
     if (st != RKL_OK) return st;
+    if ((st = check_ghosts(p, g)) != RKL_OK) return st;
     if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
     if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
@@ -674,6 +715,7 @@ rkl_status rkl_subcycle(rkl_plan_t p, int32_t g, double* T, const void* b, doubl
                         int64_t* nsub_out, void* stream) {
     rkl_status st = check_grid(p, g);
     if (st != RKL_OK) return st;
+    if ((st = check_ghosts(p, g)) != RKL_OK) return st;
     if (nsub_out) *nsub_out = 0;
     if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
     if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
@@ -710,6 +752,7 @@ rkl_status rkl_aag(rkl_plan_t p, int32_t g, double* T, const void* b, double dt_
                    int32_t* s_out, void* stream) {
     rkl_status st = check_grid(p, g);
     if (st != RKL_OK) return st;
+    if ((st = check_ghosts(p, g)) != RKL_OK) return st;
     if (s_out) *s_out = 0;
     if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
     if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
@@ -744,6 +787,7 @@ rkl_status rkl_autotune(rkl_plan_t p, int32_t g, const double* T, const void* b,
                         int32_t* best_variant, double* best_ms, void* stream) {
     rkl_status st = check_grid(p, g);
     if (st != RKL_OK) return st;
+    if ((st = check_ghosts(p, g)) != RKL_OK) return st;
     if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
     if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     if (reps < 1 || reps > 1000) return fail(RKL_EINVAL, "reps must be in [1, 1000]");
@@ -838,6 +882,7 @@ rkl_status rkl_query(rkl_plan_t p, int32_t g, int32_t* last_s, double* last_dt_p
 rkl_status rkl_superstep_batched(rkl_plan_t p, double* T, const void* b, const double* dt_hyp, int32_t* s_out,
                                  void* stream) {
     if (rkl_status st = check_plan(p)) return st;
+    if (rkl_status st = check_no_fixed(p, "the batched path")) return st;
     if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
     if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     rkl_status st = ensure_batch(p);
@@ -856,6 +901,7 @@ rkl_status rkl_superstep_batched(rkl_plan_t p, double* T, const void* b, const d
 rkl_status rkl_graph_capture(rkl_plan_t p, double* T, const void* b, const double* dt_hyp, int32_t* s_out,
                              void* stream) {
     if (rkl_status st = check_plan(p)) return st;
+    if (rkl_status st = check_no_fixed(p, "the batched path")) return st;
     if (!T || !b || !dt_hyp) return fail(RKL_EINVAL, "NULL pointer");
     if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
     rkl_status st = ensure_batch(p);

@@ -168,6 +168,8 @@ __device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int
     a.n2 = G.gc.n2;
     a.ndim = G.gc.ndim;
     a.bc = G.gc.bc;
+    a.fixed = 0;         // batched plans take no fixed axes
+    for (int i = 0; i < 6; ++i) a.gh[i] = nullptr;
     a.bx = G.bx;
     a.by = G.by;
     a.x0 = tile_x * G.bx;

@@ -25,9 +25,11 @@ struct GridConst {
     int kmode;              // 0: kappa0, 1: kappa0 T^2.5, 2: kappa0 T^kexp
     int limiter, saturation;
     int scheme;             // 0 RKL2, 1 RKL1
-    int bc;                 // bit d set: axis d is outflow, else periodic
+    int bc;                 // bit d set: axis d is outflow or fixed (indices clamp), else periodic
     double fac;             // (gamma-1)/rho
     double cp, ihsum;       // Courant number, sum_d 1/h_d^2 over active axes
+    int fixed;              // bit d set: axis d is fixed (Dirichlet ghost layers gh[2d], gh[2d+1])
+    const double* gh[6];    // ghost layers (caller's device arrays), low and high edge per axis
 };
 
 // kappa_par at a temperature, FP64, with the operation order of the scalar

@@ -104,15 +104,19 @@ hipError_t launch_finalize(const double* partials, int nblocks, const GridConst&
 }
 
 // -------------------------------------------------------- stage kernels ----
+// compile-time tile shapes for 3-D grids, runtime shapes for 1-D and 2-D
 template <typename R, int BX, int BY>
 static hipError_t launch_shape(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
-    if (P.t.ndim == 3) return launch_law<R, BX, BY, true>(P, nblocks, lim, sat, st);
-    return launch_law<R, BX, BY, false>(P, nblocks, lim, sat, st);
+    if (P.t.ndim == 3) return launch_law<R, BX, BY, 1>(P, nblocks, lim, sat, st);
+    return launch_law<R, BX, BY, 0>(P, nblocks, lim, sat, st);
 }
 
 template <typename R>
 static hipError_t launch_prec(const StageLaunch& P, int nblocks, int bx, int by, bool lim, int sat,
                               hipStream_t st) {
+    // grids with fixed axes: one runtime-shaped 16 x 16 kernel with the ghost loads
+    if (P.t.fixed) return bx == 16 && by == 16 ? launch_law<R, 16, 16, 2>(P, nblocks, lim, sat, st)
+                                               : hipErrorInvalidValue;
     if (bx == 32 && by == 8) return launch_shape<R, 32, 8>(P, nblocks, lim, sat, st);
     if (bx == 64 && by == 4) return launch_shape<R, 64, 4>(P, nblocks, lim, sat, st);
     if (bx == 16 && by == 16) return launch_shape<R, 16, 16>(P, nblocks, lim, sat, st);
@@ -123,6 +127,7 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
                         const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
                         const double* coef, hipStream_t st, double sub_scale, const Route* route) {
+    if (gc.fixed) v = Variant{16, 16, v.bz, 1};   // the tile shape of the ghost-loading kernel
     StageLaunch P;
     TileArgs& a = P.t;
     a.Yin = Yin;
@@ -141,6 +146,8 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
     a.by = v.by;
     a.kind = kind;
     a.bc = gc.bc;
+    a.fixed = gc.fixed;
+    for (int i = 0; i < 6; ++i) a.gh[i] = gc.gh[i];
     a.ih0 = gc.ih0;
     a.ih1 = gc.ih1;
     a.ih2 = gc.ih2;

@@ -71,6 +71,8 @@ extern "C" rkl_status rkl_superstep_noalloc(const rkl_grid_desc* grid, int32_t p
     if (!grid) return fail(RKL_EINVAL, "grid descriptor is NULL");
     std::string why;
     if (!validate(*grid, why)) return fail(RKL_EINVAL, why);
+    for (int d = 0; d < 3; ++d)
+        if (grid->boundary[d] == RKL_BC_FIXED) return fail(RKL_EINVAL, "rkl_superstep_noalloc does not take RKL_BC_FIXED axes");
     if (precision != RKL_FP64 && precision != RKL_MIXED) return fail(RKL_EINVAL, "precision must be RKL_FP64 or RKL_MIXED");
     const int64_t N = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
     if (N > kCells)

@@ -22,8 +22,10 @@ struct StageLaunch {
     Route route;         // route.A != NULL: Yin, Ym2, Yout chosen on the device (kinds 1, 2)
 };
 
-// FIX3: 3-D grid, tile shape fixed at compile time (run_tile's CBX, CBY)
-template <typename R, bool LIM, int SAT, int KM, int BX, int BY, bool FIX3>
+// MODE 1: 3-D grid, tile shape fixed at compile time (run_tile's CBX, CBY);
+// MODE 0: runtime tile shape; MODE 2: runtime tile shape with the ghost
+// layers of fixed axes
+template <typename R, bool LIM, int SAT, int KM, int BX, int BY, int MODE>
 __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
     constexpr int PL = (BX + 2) * (BY + 2);
     __shared__ TileLds<R, PL, (BX + 1) * BY, BX*(BY + 1)> L;
@@ -73,32 +75,34 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
         a.scale = -st->cdiv;
     }
     const FaceK<R> fk = make_facek<R>(P.kappa0, P.kexp, P.kperp, P.satq, tref);
-    if constexpr (FIX3)
+    if constexpr (MODE == 1)
         run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), BX, BY>(a, fk, tref, L);
+    else if constexpr (MODE == 2)
+        run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), 0, 0, true>(a, fk, tref, L);
     else
         run_tile<R, LIM, SAT, KM>(a, fk, tref, L);
 }
 
 // Launch helpers: the kernel of one tile shape, chosen by saturation form,
 // limiter and conductivity law.
-template <typename R, bool LIM, int KM, int BX, int BY, bool FIX3>
+template <typename R, bool LIM, int KM, int BX, int BY, int MODE>
 static void launch_sat(const StageLaunch& P, int nblocks, int sat, hipStream_t st) {
-    if (sat == 2) stage_kernel<R, LIM, 2, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
-    else if (sat == 1) stage_kernel<R, LIM, 1, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
-    else stage_kernel<R, LIM, 0, KM, BX, BY, FIX3><<<nblocks, BX * BY, 0, st>>>(P);
+    if (sat == 2) stage_kernel<R, LIM, 2, KM, BX, BY, MODE><<<nblocks, BX * BY, 0, st>>>(P);
+    else if (sat == 1) stage_kernel<R, LIM, 1, KM, BX, BY, MODE><<<nblocks, BX * BY, 0, st>>>(P);
+    else stage_kernel<R, LIM, 0, KM, BX, BY, MODE><<<nblocks, BX * BY, 0, st>>>(P);
 }
 
-template <typename R, int KM, int BX, int BY, bool FIX3>
+template <typename R, int KM, int BX, int BY, int MODE>
 static void launch_fix(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
-    if (lim) launch_sat<R, true, KM, BX, BY, FIX3>(P, nblocks, sat, st);
-    else launch_sat<R, false, KM, BX, BY, FIX3>(P, nblocks, sat, st);
+    if (lim) launch_sat<R, true, KM, BX, BY, MODE>(P, nblocks, sat, st);
+    else launch_sat<R, false, KM, BX, BY, MODE>(P, nblocks, sat, st);
 }
 
-template <typename R, int BX, int BY, bool FIX3>
+template <typename R, int BX, int BY, int MODE>
 static hipError_t launch_law(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
-    if (P.kmode == 0) launch_fix<R, 0, BX, BY, FIX3>(P, nblocks, lim, sat, st);
-    else if (P.kmode == 1) launch_fix<R, 1, BX, BY, FIX3>(P, nblocks, lim, sat, st);
-    else launch_fix<R, 2, BX, BY, FIX3>(P, nblocks, lim, sat, st);
+    if (P.kmode == 0) launch_fix<R, 0, BX, BY, MODE>(P, nblocks, lim, sat, st);
+    else if (P.kmode == 1) launch_fix<R, 1, BX, BY, MODE>(P, nblocks, lim, sat, st);
+    else launch_fix<R, 2, BX, BY, MODE>(P, nblocks, lim, sat, st);
     return hipGetLastError();
 }
 

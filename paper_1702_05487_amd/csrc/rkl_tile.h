@@ -186,7 +186,9 @@ struct TileArgs {
     int x0, y0, z0, z1;  // tile origin and z range [z0, z1)
     int bx, by;          // tile shape (bx*by <= threads, 2bx+2by+4 <= threads)
     int kind;
-    int bc;              // bit d set: axis d is outflow, else periodic
+    int bc;              // bit d set: axis d is outflow or fixed (indices clamp), else periodic
+    int fixed;           // bit d set: axis d is fixed; temperatures beyond its edges from gh[2d], gh[2d+1]
+    const double* gh[6]; // ghost layers of the fixed axes (runtime-shaped tiles only)
     double ih0, ih1, ih2;
     double scale;        // multiplies div F: -(gamma-1)/rho (kind 0) or -tau (gamma-1)/rho
     double mu, nu, omn, mut, gt;
@@ -221,6 +223,52 @@ __device__ __forceinline__ int bidx(int i, int n, bool open) {
     return open ? min(max(i, 0), n - 1) : wrap(i, n);
 }
 
+// ---------------------------------------------- fixed (Dirichlet) axes ----
+// A column of the tile beyond an x or y edge of a fixed axis reads its
+// temperatures from that axis's ghost layer (the lower axis first); a column
+// inside reads the field, and the ghost layer of a fixed z axis beyond the z
+// edges.  Layer of axis d: (n_b + 2) x (n_a + 2) values, a < b the other
+// axes, transverse index j at j + 1, wrapped on a periodic axis, clamped to
+// [0, n-1] on an outflow one and to [-1, n] on a fixed one.
+struct GhostCol {
+    const double* lp;    // layer column: plane k at lp[(k' + 1) * ls], k' the mapped z index
+    int ls;
+    const double* zlo;   // field column: the fixed z axis's ghost values below and above
+    const double* zhi;
+};
+
+__device__ __forceinline__ int gmap(int i, int n, bool clamp, bool fixed) {
+    if (!clamp) return wrap(i, n);
+    return fixed ? min(max(i, -1), n) : min(max(i, 0), n - 1);
+}
+
+__device__ inline GhostCol ghost_col(int bc, int fixed, const double* const* gh, int n0, int n1, int gi, int gj) {
+    GhostCol c{nullptr, 0, nullptr, nullptr};
+    const bool cx = bc & 1, cy = bc & 2, fx = fixed & 1, fy = fixed & 2;
+    // constant indices only (a computed index would put the array in scratch)
+    if (fx && (gi < 0 || gi >= n0)) {
+        c.lp = (gi < 0 ? gh[0] : gh[1]) + (gmap(gj, n1, cy, fy) + 1);
+        c.ls = n1 + 2;
+    } else if (fy && (gj < 0 || gj >= n1)) {
+        c.lp = (gj < 0 ? gh[2] : gh[3]) + (gmap(gi, n0, cx, fx) + 1);
+        c.ls = n0 + 2;
+    } else if (fixed & 4) {
+        const int off = (gmap(gj, n1, cy, fy) + 1) * (n0 + 2) + gmap(gi, n0, cx, fx) + 1;
+        c.zlo = gh[4] + off;
+        c.zhi = gh[5] + off;
+    }
+    return c;
+}
+
+// temperature of column c (field index xy) at plane k, any k
+__device__ inline double ghost_T(const GhostCol& c, const double* Y, int k, int n2, bool cz, bool fz, int xy,
+                                 size_t plane) {
+    if (c.lp) return c.lp[(size_t)(gmap(k, n2, cz, fz) + 1) * c.ls];
+    if (fz && k < 0) return *c.zlo;
+    if (fz && k >= n2) return *c.zhi;
+    return Y[(size_t)bidx(k, n2, cz) * plane + xy];
+}
+
 template <typename R>
 __device__ __forceinline__ R to_r(double v, double tref) {
     return R(v - tref);
@@ -236,7 +284,9 @@ __device__ __forceinline__ double stage_combine(double mu, double nu, double omn
 // CBX, CBY > 0: the tile shape is a compile-time constant, the grid is 3-D
 // and the workgroup has exactly CBX*CBY threads (one cell each); the tile
 // strides are then constants and the face code has no runtime branches.
-template <typename R, bool LIM, int SAT, int KM, int PLMAX, int FXMAX, int FYMAX, int CBX = 0, int CBY = 0>
+// GH: the ghost-layer loads of fixed axes (runtime shapes only)
+template <typename R, bool LIM, int SAT, int KM, int PLMAX, int FXMAX, int FYMAX, int CBX = 0, int CBY = 0,
+          bool GH = false>
 __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, double tref,
                                          TileLds<R, PLMAX, FXMAX, FYMAX>& L) {
     constexpr bool FIX = CBX > 0;
@@ -270,7 +320,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     const bool hjob = tid < ne + 4;
     const bool djob = tid < ne;
     bool dxh = false;
-    int hslot = 0, hxy = 0;
+    int hslot = 0, hxy = 0, hti = 0, htj = 0;
     if (hjob) {
         int hi, hj;
         if (tid < bx) { hi = tid; hj = -1; }
@@ -284,6 +334,8 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
         }
         hslot = (hj + 1) * px + hi + 1;
         hxy = bidx(a.y0 + hj, n1, oy) * n0 + bidx(a.x0 + hi, n0, ox);
+        hti = hi;
+        htj = hj;
     }
     // extra face: the tile's -x face of row j (f < by) or -y face of column i.
     // These jobs go to the last wave(s) of the workgroup while the halo jobs
@@ -302,6 +354,21 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     const int z0 = a.z0, z1 = a.z1;
     // index of plane k + 4, the temperature plane prefetched at plane k
     int pz4 = bidx(z0 + 2, n2, oz);
+
+    // fixed axes: ghost-aware temperature loads of the own and halo columns
+    const bool gon = GH && !FIX && a.fixed != 0;
+    GhostCol gco{nullptr, 0, nullptr, nullptr}, gch{nullptr, 0, nullptr, nullptr};
+    if (gon) {
+        gco = ghost_col(a.bc, a.fixed, a.gh, n0, n1, a.x0 + tx, a.y0 + ty);
+        if (hjob) {
+            gch = ghost_col(a.bc, a.fixed, a.gh, n0, n1, a.x0 + hti, a.y0 + htj);
+        }
+    }
+    const bool fz = a.fixed & 4;
+    // T at plane k (raw index), field index xy, through column g where ghosts apply
+    auto tld = [&](const double* pp, int k, int xy, const GhostCol& g) -> double {
+        return gon ? ghost_T(g, a.Yin, k, n2, oz, fz, xy, (size_t)plane) : pp[xy];
+    };
 
     // Prefetch pipeline, two planes deep: set 0 is stored into LDS at this
     // plane's step A, set 1 at the next plane's.  Values stay in their loaded
@@ -336,17 +403,17 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
         const size_t pb0 = (size_t)bidx(z0 - 1, n2, oz) * plane;
         const size_t pb1 = (size_t)bidx(z0, n2, oz) * plane;
         if (own) {
-            yq1 = p0[oxy];
-            yq2 = p1[oxy];
-            pTo0 = p2[oxy];
-            pTo1 = p3[oxy];
+            yq1 = tld(p0, z0 - 2, oxy, gco);
+            yq2 = tld(p1, z0 - 1, oxy, gco);
+            pTo0 = tld(p2, z0, oxy, gco);
+            pTo1 = tld(p3, z0 + 1, oxy, gco);
             pbo00 = b0[pb0 + oxy]; pbo01 = b1[pb0 + oxy]; pbo02 = b2[pb0 + oxy];
             pbo10 = b0[pb1 + oxy]; pbo11 = b1[pb1 + oxy]; pbo12 = b2[pb1 + oxy];
         }
         if (hjob) {
-            const double h1 = p0[hxy], h2 = p1[hxy];
-            pTh0 = p2[hxy];
-            pTh1 = p3[hxy];
+            const double h1 = tld(p0, z0 - 2, hxy, gch), h2 = tld(p1, z0 - 1, hxy, gch);
+            pTh0 = tld(p2, z0, hxy, gch);
+            pTh1 = tld(p3, z0 + 1, hxy, gch);
             hq1 = to_r<R>(h1, tref);
             hq2 = to_r<R>(h2, tref);
             L.T[0][hslot] = hq1;
@@ -389,10 +456,10 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
             const int pbz = oz ? min(k + 3, n2 - 1) : (pz4 == 0 ? n2 - 1 : pz4 - 1);
             const size_t pb = (size_t)pbz * plane;
             if (own) {
-                pTo1 = pt[oxy];
+                pTo1 = tld(pt, k + 4, oxy, gco);
                 pbo10 = b0[pb + oxy]; pbo11 = b1[pb + oxy]; pbo12 = b2[pb + oxy];
             }
-            if (hjob) pTh1 = pt[hxy];
+            if (hjob) pTh1 = tld(pt, k + 4, hxy, gch);
             if (djob) { pbd10 = b0[pb + hxy]; pbd11 = b1[pb + hxy]; pbd12 = b2[pb + hxy]; }
             pz4 = oz ? min(k + 5, n2 - 1) : (pz4 + 1 == n2 ? 0 : pz4 + 1);
         }

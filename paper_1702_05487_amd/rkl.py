@@ -19,12 +19,12 @@ RKL_OK, RKL_EINVAL, RKL_ENOMEM, RKL_EDEVICE, RKL_ESTAGES, RKL_ESTATE = range(6)
 RKL_FP64, RKL_MIXED = 0, 1
 RKL_LIM_NONE, RKL_LIM_MC = 0, 1
 RKL_SAT_NONE, RKL_SAT_CENTRAL, RKL_SAT_UPWIND = 0, 1, 2
-RKL_BC_PERIODIC, RKL_BC_OUTFLOW = 0, 1
+RKL_BC_PERIODIC, RKL_BC_OUTFLOW, RKL_BC_FIXED = 0, 1, 2
 RKL_RKL2, RKL_RKL1 = 0, 1
 RKL_FLAG_NONPOS, RKL_FLAG_NONFINITE, RKL_FLAG_STAGES, RKL_FLAG_ABORTED = 1, 2, 4, 8
 
 EXPORTS = [
-    "rkl_plan", "rkl_destroy", "rkl_grid_offset", "rkl_flux_div", "rkl_dt_par",
+    "rkl_plan", "rkl_destroy", "rkl_grid_offset", "rkl_set_ghosts", "rkl_flux_div", "rkl_dt_par",
     "rkl_superstep", "rkl_superstep_async", "rkl_superstep_noalloc", "rkl_superstep_batched", "rkl_graph_capture", "rkl_graph_launch",
     "rkl_query", "rkl_variant_count", "rkl_variant_info", "rkl_set_variant", "rkl_last_error",
     "rkl_profile", "rkl_profile_read", "rkl_autotune",
@@ -87,6 +87,7 @@ def load(build_if_missing: bool = True):
         "rkl_plan": (i32, [P(rkl_grid_desc), i32, P(rkl_options), P(vp)]),
         "rkl_destroy": (i32, [vp]),
         "rkl_grid_offset": (i64, [vp, i32]),
+        "rkl_set_ghosts": (i32, [vp, i32, i32, vp, vp]),
         "rkl_flux_div": (i32, [vp, i32, vp, vp, vp, vp]),
         "rkl_dt_par": (i32, [vp, i32, vp, P(dbl), vp]),
         "rkl_superstep": (i32, [vp, i32, vp, vp, dbl, P(i32), vp]),
@@ -226,6 +227,17 @@ def rkl_variant_info(v):
 
 def rkl_set_variant(plan, v):
     _check(load().rkl_set_variant(plan, v))
+
+
+def rkl_set_ghosts(plan, grid, axis, lo_ptr, hi_ptr):
+    _check(load().rkl_set_ghosts(plan, grid, axis, lo_ptr, hi_ptr))
+
+
+def ghost_shape(n, axis):
+    """shape of one ghost layer of a fixed axis of a grid of n = (n0, n1, n2)
+    cells: (n_b + 2, n_a + 2), a < b the other two axes"""
+    a, b = [e for e in range(3) if e != axis]
+    return (n[b] + 2, n[a] + 2)
 
 
 def rkl_stream(src_ptr, dst_ptr, nbytes, mode, stream):
@@ -396,6 +408,24 @@ class Plan:
 
     def set_variant(self, v):
         rkl_set_variant(self.handle, v)
+
+    def set_ghosts(self, axis, lo, hi, grid=0):
+        """Ghost temperatures beyond the low and high edge of fixed axis
+        `axis`: float64 device tensors of ghost_shape(n, axis).  The plan
+        reads them at every later stencil call; they are kept referenced
+        here so that they stay alive."""
+        import torch
+        d = self.descs[grid]
+        shape = ghost_shape(tuple(d.n), axis)
+        ptrs = []
+        for name, t in (("lo", lo), ("hi", hi)):
+            if tuple(t.shape) != shape:
+                raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), shape))
+            ptrs.append(_dev_ptr(t, torch.float64, shape[0] * shape[1], name))
+        rkl_set_ghosts(self.handle, grid, axis, ptrs[0], ptrs[1])
+        if not hasattr(self, "_ghosts"):
+            self._ghosts = {}
+        self._ghosts[(grid, axis)] = (lo, hi)
 
     def autotune(self, T, b, dt_hyp, reps=2, grid=0, cache=None):
         """Pick the fastest stencil variant for this grid (see tune.py for the

@@ -49,7 +49,8 @@ def test_descriptor_struct_matches_header(tmp_path):
     dict(ndim=4), dict(n=(0, 4, 4)), dict(n=(4, 4, 2), ndim=2), dict(h=(0.0, 1, 1)),
     dict(limiter=2), dict(saturation=1, phi=0.0), dict(saturation=2, phi=0.0), dict(saturation=3),
     dict(saturation=-1), dict(kappa0=-1.0), dict(kappa_exp=-0.5),
-    dict(boundary=(2, 0, 0)), dict(boundary=(0, -1, 0)),
+    dict(boundary=(3, 0, 0)), dict(boundary=(0, -1, 0)), dict(n=(8, 8, 1), ndim=2, boundary=(0, 0, 2)),
+    dict(n=(8, 1, 1), ndim=1, boundary=(2, 2, 0)),
     dict(kperp_ratio=1.5), dict(rho=0.0), dict(gamma=1.0), dict(cp=0.6), dict(cp=0.0),
 ])
 def test_invalid_descriptors_are_rejected(bad):
@@ -165,3 +166,17 @@ def test_noalloc_refuses_sizes_beyond_its_static_scratch():
         assert "RKL_NOALLOC_MAX_STAGES" in str(e.value)
     with pytest.raises(rkl.RklError):
         rkl.rkl_superstep_noalloc(small, 7, ctypes.c_void_p(256), ctypes.c_void_p(4096), 1e-6, 8, None, None)
+    fixed = rkl.grid_desc((8, 8, 8), (0.1, 0.1, 0.1), ndim=3, boundary=(0, rkl.RKL_BC_FIXED, 0))
+    with pytest.raises(rkl.RklError) as e:
+        rkl.rkl_superstep_noalloc(fixed, rkl.RKL_FP64, ctypes.c_void_p(256), ctypes.c_void_p(4096), 1e-6, 8,
+                                  None, None)
+    assert e.value.status == rkl.RKL_EINVAL and "RKL_BC_FIXED" in str(e.value)
+
+
+def test_set_ghosts_checks_its_arguments_on_the_host():
+    import ctypes
+    with pytest.raises(rkl.RklError) as e:
+        rkl.rkl_set_ghosts(None, 0, 0, ctypes.c_void_p(256), ctypes.c_void_p(512))
+    assert e.value.status == rkl.RKL_EINVAL
+    assert rkl.ghost_shape((5, 4, 3), 0) == (5, 6) and rkl.ghost_shape((5, 4, 3), 1) == (5, 7)
+    assert rkl.ghost_shape((5, 4, 3), 2) == (6, 7)

@@ -126,7 +126,7 @@ def test_outflow_every_variant_same_bits(torch_cuda, precision):
     ratio = inputs.midpoint_ratio(8)
     base = run(torch_cuda, "3d_xz_open_ragged", precision, ratio, variant=0)[0]
     for v in range(1, rkl.rkl_variant_count()):
-        if rkl.rkl_variant_info(v)[3] == 2:
+        if rkl.rkl_variant_info(v)[3] >= 2:
             continue
         assert np.array_equal(run(torch_cuda, "3d_xz_open_ragged", precision, ratio, variant=v)[0], base), v
 

@@ -47,7 +47,7 @@ def draw(k):
     precision = "mixed" if fused_case or rng.random() < 0.5 else "fp64"
     periodic3d = ndim == 3 and not any(p["boundary"])
     fused = fused_case or (precision == "mixed" and periodic3d and rng.random() < 0.5)
-    choices = [v for v in range(rkl.rkl_variant_count()) if rkl.rkl_variant_info(v)[3] == (2 if fused else 1)]
+    choices = [v for v in range(rkl.rkl_variant_count()) if (rkl.rkl_variant_info(v)[3] >= 2) == fused]
     variant = int(rng.choice(choices))
     s = int(rng.integers(2, 13))
     shape = (n[2], n[1], n[0])
@@ -143,8 +143,8 @@ def test_random_configuration_other_integrators(torch_cuda, k, method):
     torch = torch_cuda
     from paper_1702_05487_amd import rkl
     n, h, ndim, p, precision, variant, s, T, b = draw(k)
-    if rkl.rkl_variant_info(variant)[3] == 2:
-        variant = 0                      # two-stage launches are an RKL2 form
+    if rkl.rkl_variant_info(variant)[3] >= 2:
+        variant = 0                      # fused launches are an RKL2 form
     tol = 1e-12 if precision == "fp64" else 1e-5
     bg = b.astype(np.float32) if precision == "mixed" else b
     bt = torch.float32 if precision == "mixed" else torch.float64
