@@ -71,4 +71,9 @@ def test_committed_traffic_files_are_well_formed(name):
     kind = "p" if d["kernel"] == "batch_stage_kernel" else "v"
     assert name.endswith("_%s%d_traffic.json" % (kind, d["variant"]))
     assert d["bytes_per_launch"] == pytest.approx(d["read_bytes_per_launch"] + d["write_bytes_per_launch"])
-    assert 1.9 < d["fetch_factor"] < 2.1 and 0.9 < d["write_factor"] < 1.1
+    # request counters of a 1 GiB streaming copy count 1 GiB each way
+    assert 0.99 < d["calibration_copy_read_over_1GiB"] < 1.01
+    assert 0.99 < d["calibration_copy_write_over_1GiB"] < 1.01
+    # taken on the current kernel sources (else bench.py reports no traffic)
+    fuse = {"stage_kernel": 1, "fused_kernel": 2, "batch_stage_kernel": "batch"}[d["kernel"]]
+    assert d["kernel_hash"] == bench.kernel_hash(fuse)
