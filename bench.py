@@ -187,6 +187,24 @@ def copy_ceiling(torch):
     return gbs
 
 
+def stream_ceiling(torch, rkl):
+    """Bandwidth of the library's streaming copy kernel (rkl_stream, 8-byte
+    lanes, 2 GiB source and destination; read + write bytes per second): the
+    highest copy rate measured on this GPU, for reference."""
+    src = torch.ones(1 << 28, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    rkl.stream_probe(src, dst, 0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        rkl.stream_probe(src, dst, 0)
+    e1.record()
+    e1.synchronize()
+    gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    return gbs
+
+
 def bench_batched(args, torch, inputs, rkl, precision="mixed", loop=False):
     """2000 independent periodic patches (edges log-uniform in [16, 64], own
     fields, dt_hyp for s_p uniform in [4, 40]), one super-step of all of them
@@ -786,6 +804,13 @@ def main():
     ceil = copy_ceiling(torch)
     out["roofline"]["copy_GBs"] = ceil
     out["roofline"]["frac_of_copy"] = r["achieved"] / ceil
+    sc = stream_ceiling(torch, rkl)
+    out["roofline"]["stream_copy_GBs"] = sc
+    out["roofline"]["frac_of_stream_copy"] = r["achieved"] / sc
+    if traffic:
+        # counted HBM bytes of the dominant kernel per second of its launches
+        out["roofline"]["traffic_GBs"] = traffic / (r["avg_launch_ms"] / 1e3) / 1e9
+        out["roofline"]["traffic_frac_of_stream_copy"] = out["roofline"]["traffic_GBs"] / sc
     if not args.no_cpu_baseline:
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
         out["cpu_baseline"], out["accuracy"] = horizon_check(w, precision, torch, rkl, threads)
