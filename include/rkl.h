@@ -70,7 +70,13 @@ enum { RKL_SAT_NONE = 0, RKL_SAT_CENTRAL = 1, RKL_SAT_UPWIND = 2 };
  * test's edge values from the exact solution). */
 enum { RKL_BC_PERIODIC = 0, RKL_BC_OUTFLOW = 1, RKL_BC_FIXED = 2 };
 
-/* flag bits reported by rkl_query */
+/* flag bits reported by rkl_query.  RKL_FLAG_NONPOS reports the negative
+ * temperatures the paper warns about: unlimited transverse gradients can
+ * drive T below zero near large gradients (Sec. 4.1.3, and the local
+ * thermal instability runs of Sec. 4.2.2, which blow up without limiters),
+ * and the paper recommends the limiter once T falls below a floor.  The
+ * library applies no floor; the flag lets the caller switch to the MC
+ * limiter or floor T. */
 enum {
     RKL_FLAG_NONPOS = 1u,     /* some input temperature <= 0 (conductivity clipped at 0) */
     RKL_FLAG_NONFINITE = 2u,  /* some input temperature is NaN or infinite */
