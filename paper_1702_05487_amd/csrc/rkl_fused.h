@@ -84,7 +84,7 @@ __device__ __forceinline__ void run_fused(const FusedArgs& a, const FaceK<R>& fk
     const R* b2 = b1 + N;
     const R* M0 = (const R*)a.MY0;
     const R ih0 = R(a.ih0), ih1 = R(a.ih1), ih2 = R(a.ih2);
-    const R hih0 = R(0.5 * a.ih0), hih1 = R(0.5 * a.ih1), hih2 = R(0.5 * a.ih2);
+    const R hih0 = R(0.25 * a.ih0), hih1 = R(0.25 * a.ih1), hih2 = R(0.25 * a.ih2);   // 1/(4h), see cell_slope
 
     // own cell: region coordinates (tx, ty); the region starts F-1 cells
     // before the output tile along x and y

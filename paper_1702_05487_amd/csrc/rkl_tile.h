@@ -85,19 +85,23 @@ __device__ __forceinline__ double mc2(double a, double b) {
     return copysign(fmin(4.0 * fabs(m), fabs(a + b)), m);
 }
 
-// Cell slope along one axis from the one-sided differences (t0-tm)/h and
-// (tp-t0)/h: MC-limited, or their mean (so that the mean of two cell slopes
-// is the mean of the four one-sided differences of Appendix B).  hih = 1/(2h).
+// Half the cell slope along one axis, from the one-sided differences
+// (t0-tm)/h and (tp-t0)/h: MC-limited, or their mean (so that the mean of two
+// cell slopes is the mean of the four one-sided differences of Appendix B).
+// hq = 1/(4h).  The slope is stored halved so that the face's transverse
+// gradient below, MC or mean of the two cells' slopes, needs no halving:
+// MC and the sum are positively homogeneous and halving is exact, so the
+// result has the same bits as halving at the face.
 template <typename R, bool LIM>
-__device__ __forceinline__ R cell_slope(R tm, R t0, R tp, R hih) {
-    if (LIM) return hih * mc2(t0 - tm, tp - t0);
-    return hih * (tp - tm);
+__device__ __forceinline__ R cell_slope(R tm, R t0, R tp, R hq) {
+    if (LIM) return hq * mc2(t0 - tm, tp - t0);
+    return hq * (tp - tm);
 }
 
-// transverse gradient at a face from the slopes of its two cells
+// transverse gradient at a face from the (halved) slopes of its two cells
 template <typename R, bool LIM>
 __device__ __forceinline__ R face_transverse(R sL, R sR) {
-    return R(0.5) * (LIM ? mc2(sL, sR) : sL + sR);
+    return LIM ? mc2(sL, sR) : sL + sR;
 }
 
 // per-grid constants of the face flux, in the flux precision
@@ -169,7 +173,7 @@ __device__ __forceinline__ R face_flux(R TL, R TR, R ihn, R sL1, R sR1, R sL2, R
     } else {
         q = k.satq * t15;
     }
-    const R den = fma(kpar, r_sqrt(fmax(B2, R(0))), q);    // q + |F|
+    const R den = fma(kpar, r_sqrt(B2), q);    // q + |F|; B2 >= 0: sums of products of non-negative terms
     return den > R(0) ? -(kpar * A) * (q * r_rcp(den)) : R(0);
 }
 
@@ -301,7 +305,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
     const R* b1 = b0 + N;
     const R* b2 = b1 + N;
     const R ih0 = R(a.ih0), ih1 = R(a.ih1), ih2 = R(a.ih2);
-    const R hih0 = R(0.5 * a.ih0), hih1 = R(0.5 * a.ih1), hih2 = R(0.5 * a.ih2);
+    const R hih0 = R(0.25 * a.ih0), hih1 = R(0.25 * a.ih1), hih2 = R(0.25 * a.ih2);   // 1/(4h), see cell_slope
     const bool do_y = FIX || a.ndim >= 2, do_z = FIX || a.ndim >= 3;
     const bool ox = a.bc & 1, oy = a.bc & 2, oz = a.bc & 4;
 

@@ -87,9 +87,11 @@ def check(torch, precision, variants):
               % (precision, v, np.abs(got - ref).max(), np.abs(ref - t0).max(), rel_l1(got - t0, ref - t0)),
               flush=True)
         # the change over one super-step at h = 1/2048 is ~3e-8 of T, so one
-        # FP64 rounding of T (~2e-16) is already ~1e-8 of the change
+        # FP64 rounding of T (~2e-16) is already ~1e-8 of the change, and the
+        # FP32 flux arithmetic (2^-24 of the offset temperatures, ~6e-9 here)
+        # a few 1e-3 of it (3.9e-3 measured; 1e-10 absolute)
         if precision == "mixed":
-            assert np.abs(got - ref).max() <= 4e-5
+            assert np.abs(got - ref).max() <= 1e-8
             assert rel_l1(got - t0, ref - t0) <= 1e-2
         else:
             assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()

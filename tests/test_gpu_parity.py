@@ -261,8 +261,13 @@ def test_spitzer_256_sampled_full_size(torch_cuda, precision, tol):
         s = plan.superstep(Td, bd, dt)
         assert s == oracle.stages(w.ratio) == 16
         got = Td.cpu().numpy()[tuple(np.array(centers).T)]
-        assert np.abs(got - ref).max() <= tol * 4, v
-        assert rel_l1(got - T0, ref - T0) <= (1e-9 if precision == "fp64" else 1e-2), v
+        print("  %s variant %d: max |diff| %.3e, change rel-L1 %.3e"
+              % (precision, v, np.abs(got - ref).max(), rel_l1(got - T0, ref - T0)), flush=True)
+        # mixed: T ~ 1, FP32 flux arithmetic on temperatures offset to their
+        # mean leaves ~1e-7 at the worst cell of the whole field (1.8e-7
+        # measured there), so 1e-6 absolute and 1e-5 of the change
+        assert np.abs(got - ref).max() <= (4e-12 if precision == "fp64" else 1e-6), v
+        assert rel_l1(got - T0, ref - T0) <= (1e-9 if precision == "fp64" else 1e-5), v
         if first is None:
             first = Td
         else:
@@ -287,8 +292,10 @@ def test_saturated_512_sampled_full_size(torch_cuda, precision, variants):
     s = 24: one full-size super-step with the one-stage variants bench.py
     times (32x8 tiles, z-chunks 32 and 64) against the oracle at sampled
     cells (periodic windows of half-width s+1, which hold the centre cell's
-    whole dependency cone).  Mixed: max |diff| <= 4e-5; FP64: rounding
-    level, max |diff| <= 1e-12 |T|."""
+    whole dependency cone).  Mixed: max |diff| <= 1e-6 (T ~ 1; FP32 flux
+    arithmetic on offset temperatures leaves ~1e-7 at the worst cell) and
+    rel-L1 of the change <= 1e-5; FP64: rounding level, max |diff| <=
+    1e-12 |T|."""
     torch = torch_cuda
     from paper_1702_05487_amd import rkl
     w = inputs.saturated_512(fields=False)
@@ -315,8 +322,8 @@ def test_saturated_512_sampled_full_size(torch_cuda, precision, variants):
         got = T[idx].cpu().numpy()
         print("  %s variant %d: max |diff| %.3e" % (precision, v, np.abs(got - ref).max()), flush=True)
         if precision == "mixed":
-            assert np.abs(got - ref).max() <= 4e-5
-            assert rel_l1(got - t0, ref - t0) <= 1e-2
+            assert np.abs(got - ref).max() <= 1e-6
+            assert rel_l1(got - t0, ref - t0) <= 1e-5
         else:
             assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
             assert rel_l1(got - t0, ref - t0) <= 1e-9

@@ -163,8 +163,9 @@ def test_upwind_fused_768_sampled(torch_cuda):
         outs.append(T)
         print("  upwind 768^3 variant %d: max |diff| %.3e, change rel-L1 %.3e"
               % (v, np.abs(got - ref).max(), rel_l1(got - t0, ref - t0)), flush=True)
-        assert np.abs(got - ref).max() <= 4e-5
-        assert rel_l1(got - t0, ref - t0) <= 1e-2
+        # T ~ 1: FP32 flux arithmetic on offset temperatures leaves ~1e-7
+        assert np.abs(got - ref).max() <= 1e-6
+        assert rel_l1(got - t0, ref - t0) <= 1e-5
     assert torch.equal(outs[0], outs[1])
     plan.close()
 
