@@ -51,7 +51,9 @@ _FUSED_SOURCES = ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/
                   "paper_1702_05487_amd/csrc/rkl_fused.hip"]
 KERNEL_SOURCES = {
     1: ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_stage.h",
-        "paper_1702_05487_amd/csrc/rkl_kernels.hip"],
+        "paper_1702_05487_amd/csrc/rkl_kernels.hip"]
+       + ["paper_1702_05487_amd/csrc/rkl_stage_%s.hip" % u
+          for u in ("f32_32x8", "f32_64x4", "f32_16x16", "f64_32x8", "f64_64x4", "f64_16x16")],
     2: _FUSED_SOURCES, 3: _FUSED_SOURCES, 4: _FUSED_SOURCES,
     "batch": ["paper_1702_05487_amd/csrc/rkl_tile.h", "paper_1702_05487_amd/csrc/rkl_batch.hip"],
 }

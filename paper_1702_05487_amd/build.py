@@ -14,7 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "librkl.so")
-SOURCES = ["rkl_kernels.hip", "rkl_fused.hip", "rkl_batch.hip", "rkl_api.hip", "rkl_noalloc.hip", "rkl_stream.hip"]
+SOURCES = ["rkl_stage_f64_32x8.hip", "rkl_stage_f64_64x4.hip", "rkl_stage_f64_16x16.hip",
+           "rkl_stage_f32_32x8.hip", "rkl_stage_f32_64x4.hip", "rkl_stage_f32_16x16.hip",
+           "rkl_kernels.hip", "rkl_fused.hip", "rkl_batch.hip", "rkl_api.hip", "rkl_noalloc.hip", "rkl_stream.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -104,18 +104,12 @@ hipError_t launch_finalize(const double* partials, int nblocks, const GridConst&
 }
 
 // -------------------------------------------------------- stage kernels ----
-// compile-time tile shapes for 3-D grids, runtime shapes for 1-D and 2-D
-template <typename R, int BX, int BY>
-static hipError_t launch_shape(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
-    if (P.t.ndim == 3) return launch_law<R, BX, BY, 1>(P, nblocks, lim, sat, st);
-    return launch_law<R, BX, BY, 0>(P, nblocks, lim, sat, st);
-}
-
+// (instantiated in the rkl_stage_*.hip units)
 template <typename R>
 static hipError_t launch_prec(const StageLaunch& P, int nblocks, int bx, int by, bool lim, int sat,
                               hipStream_t st) {
     // grids with fixed axes: one runtime-shaped 16 x 16 kernel with the ghost loads
-    if (P.t.fixed) return bx == 16 && by == 16 ? launch_law<R, 16, 16, 2>(P, nblocks, lim, sat, st)
+    if (P.t.fixed) return bx == 16 && by == 16 ? launch_fixed<R>(P, nblocks, lim, sat, st)
                                                : hipErrorInvalidValue;
     if (bx == 32 && by == 8) return launch_shape<R, 32, 8>(P, nblocks, lim, sat, st);
     if (bx == 64 && by == 4) return launch_shape<R, 64, 4>(P, nblocks, lim, sat, st);

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
     }
     const FaceK<R> fk = make_facek<R>(P.kappa0, P.kexp, P.kperp, P.satq, tref);
     if constexpr (MODE == 1)
-        run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), BX, BY>(a, fk, tref, L);
+        run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), BX, BY, false, 6, true>(a, fk, tref, L);
     else if constexpr (MODE == 2)
         run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), 0, 0, true>(a, fk, tref, L);
     else
@@ -105,5 +105,30 @@ static hipError_t launch_law(const StageLaunch& P, int nblocks, bool lim, int sa
     else launch_fix<R, 2, BX, BY, MODE>(P, nblocks, lim, sat, st);
     return hipGetLastError();
 }
+
+// The kernels of one tile shape: compile-time shape for 3-D grids, runtime
+// shape for 1-D and 2-D ones.  Instantiated once per precision and shape in
+// the rkl_stage_*.hip units, which compile in parallel.
+template <typename R, int BX, int BY>
+hipError_t launch_shape(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
+    if (P.t.ndim == 3) return launch_law<R, BX, BY, 1>(P, nblocks, lim, sat, st);
+    return launch_law<R, BX, BY, 0>(P, nblocks, lim, sat, st);
+}
+
+// grids with fixed axes: the runtime-shaped 16 x 16 kernel with the ghost loads
+template <typename R>
+hipError_t launch_fixed(const StageLaunch& P, int nblocks, bool lim, int sat, hipStream_t st) {
+    return launch_law<R, 16, 16, 2>(P, nblocks, lim, sat, st);
+}
+
+#define RKL_SHAPE_ARGS const StageLaunch&, int, bool, int, hipStream_t
+extern template hipError_t launch_shape<float, 32, 8>(RKL_SHAPE_ARGS);
+extern template hipError_t launch_shape<float, 64, 4>(RKL_SHAPE_ARGS);
+extern template hipError_t launch_shape<float, 16, 16>(RKL_SHAPE_ARGS);
+extern template hipError_t launch_shape<double, 32, 8>(RKL_SHAPE_ARGS);
+extern template hipError_t launch_shape<double, 64, 4>(RKL_SHAPE_ARGS);
+extern template hipError_t launch_shape<double, 16, 16>(RKL_SHAPE_ARGS);
+extern template hipError_t launch_fixed<float>(RKL_SHAPE_ARGS);
+extern template hipError_t launch_fixed<double>(RKL_SHAPE_ARGS);
 
 }  // namespace rkl

@@ -29,6 +29,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 // No automatic contraction of a*b+c: every fused multiply-add below is
 // written out, so each tile shape, kernel variant and the batched kernels
@@ -288,9 +289,14 @@ __device__ __forceinline__ double stage_combine(double mu, double nu, double omn
 // CBX, CBY > 0: the tile shape is a compile-time constant, the grid is 3-D
 // and the workgroup has exactly CBX*CBY threads (one cell each); the tile
 // strides are then constants and the face code has no runtime branches.
-// GH: the ghost-layer loads of fixed axes (runtime shapes only)
+// GH: the ghost-layer loads of fixed axes (runtime shapes only).
+// UNR: the plane loop unrolled six-fold (6) or not (1); see the register
+// rings below.  NT: the pointwise stage inputs and the stage output, each
+// touched once per launch, bypass the caches' normal retention so that the
+// lines that neighbouring tiles share (temperatures, unit vectors) stay.
+// Neither changes a value.
 template <typename R, bool LIM, int SAT, int KM, int PLMAX, int FXMAX, int FYMAX, int CBX = 0, int CBY = 0,
-          bool GH = false>
+          bool GH = false, int UNR = 1, bool NT = false>
 __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, double tref,
                                          TileLds<R, PLMAX, FXMAX, FYMAX>& L) {
     constexpr bool FIX = CBX > 0;
@@ -374,188 +380,414 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
         return gon ? ghost_T(g, a.Yin, k, n2, oz, fz, xy, (size_t)plane) : pp[xy];
     };
 
-    // Prefetch pipeline, two planes deep: set 0 is stored into LDS at this
-    // plane's step A, set 1 at the next plane's.  Values stay in their loaded
-    // type until they are used, so that no conversion forces an early wait.
-    double pTo0 = 0.0, pTo1 = 0.0;            // T(k+2), T(k+3): own cell
-    double pTh0 = 0.0, pTh1 = 0.0;            // T(k+2), T(k+3): halo cell
-    R pbo00 = 0, pbo01 = 0, pbo02 = 0, pbo10 = 0, pbo11 = 0, pbo12 = 0;   // b(k+1), b(k+2): own
-    R pbd00 = 0, pbd01 = 0, pbd02 = 0, pbd10 = 0, pbd11 = 0, pbd12 = 0;   // b(k+1), b(k+2): halo
-    double yq0 = 0.0, yq1 = 0.0, yq2 = 0.0;   // own FP64 input, planes k, k+1, k+2
-    R oq0 = 0, oq1 = 0, oq2 = 0;              // same in flux precision
-    R hq0 = 0, hq1 = 0, hq2 = 0;              // halo cell input, planes k, k+1, k+2
-    R ob00 = 0, ob01 = 0, ob02 = 0;           // own b, plane k
-    R ob10 = 0, ob11 = 0, ob12 = 0;           // own b, plane k+1
-    R os00 = 0, os01 = 0, os02 = 0;           // own slopes, plane k
-    R os10 = 0, os11 = 0, os12 = 0;           // own slopes, plane k+1
-    R fzp = 0;                                // +z face flux of plane k-1
-    // pointwise stage inputs Y_{j-2}, Y0, tau M(Y0): plane k (cur), k+1 (q1),
-    // k+2 (q2), loaded two planes ahead
-    double ym2 = 0.0, y0v = 0.0;
-    R my0 = 0;
-    double q1ym2 = 0.0, q1y0 = 0.0, q2ym2 = 0.0, q2y0 = 0.0;
-    R q1my0 = 0, q2my0 = 0;
-    const bool pw = own && a.kind == 2;
+    if constexpr (UNR == 6) {
+        // Register rings.  The value for plane k + m sits in slot (P + m) mod L
+        // of a ring of length L, P = (k - z0 + 2) mod 6.  The loop is unrolled
+        // six-fold (every L divides six) with P a compile-time constant, so each
+        // value stays in one register from its load to its last use and no
+        // plane-to-plane moves are left.  Loads are two planes ahead, and values
+        // stay in their loaded type until they are used, so that no conversion
+        // forces an early wait.
+        constexpr int LT = 6;          // own FP64 input: planes k .. k+4
+        constexpr int LB = 6;          // own unit vector: planes k .. k+3
+        double tq[LT];                 // own input Y_{j-1}, FP64
+        R oq[3];                       // the same in flux precision: planes k .. k+2
+        double th[2];                  // halo cell input, FP64: planes k+2, k+3 (k+4 loaded into the slot of k+2)
+        R hq[3];                       // halo cell input in flux precision: planes k .. k+2
+        R ob[LB][3];                   // own unit vector
+        R pbd[2][3];                   // halo unit vector: planes k+1, k+2 (k+3 loaded into the slot of k+1)
+        R os[2][3];                    // own slopes: planes k, k+1
+        R zf[2];                       // +z face flux: planes k-1, k
+        double qym2[3], qy0[3];        // pointwise stage inputs Y_{j-2}, Y0: planes k .. k+2
+        R qmy0[3];                     // tau M(Y0): planes k .. k+2
+        for (int r = 0; r < LT; ++r) tq[r] = 0.0;
+        for (int r = 0; r < LB; ++r) ob[r][0] = ob[r][1] = ob[r][2] = 0;
+        for (int r = 0; r < 3; ++r) {
+            oq[r] = hq[r] = 0;
+            qym2[r] = qy0[r] = 0.0;
+            qmy0[r] = 0;
+        }
+        for (int r = 0; r < 2; ++r) {
+            th[r] = 0.0;
+            zf[r] = 0;
+            pbd[r][0] = pbd[r][1] = pbd[r][2] = 0;
+            os[r][0] = os[r][1] = os[r][2] = 0;
+        }
+        const bool pw = own && a.kind == 2;
 
-    // ring slots: T(k) c0, T(k+1) c1, T(k+2) c2; slopes/b of plane k in dc, of k+1 in dn
-    int c0 = 0, c1 = 1, c2 = 2, dc = 1, dn = 0, fb = 0;
-    {
-        const double* p0 = a.Yin + (size_t)bidx(z0 - 2, n2, oz) * plane;
-        const double* p1 = a.Yin + (size_t)bidx(z0 - 1, n2, oz) * plane;
-        const double* p2 = a.Yin + (size_t)bidx(z0, n2, oz) * plane;
-        const double* p3 = a.Yin + (size_t)bidx(z0 + 1, n2, oz) * plane;
-        const size_t pb0 = (size_t)bidx(z0 - 1, n2, oz) * plane;
-        const size_t pb1 = (size_t)bidx(z0, n2, oz) * plane;
-        if (own) {
-            yq1 = tld(p0, z0 - 2, oxy, gco);
-            yq2 = tld(p1, z0 - 1, oxy, gco);
-            pTo0 = tld(p2, z0, oxy, gco);
-            pTo1 = tld(p3, z0 + 1, oxy, gco);
-            pbo00 = b0[pb0 + oxy]; pbo01 = b1[pb0 + oxy]; pbo02 = b2[pb0 + oxy];
-            pbo10 = b0[pb1 + oxy]; pbo11 = b1[pb1 + oxy]; pbo12 = b2[pb1 + oxy];
-        }
-        if (hjob) {
-            const double h1 = tld(p0, z0 - 2, hxy, gch), h2 = tld(p1, z0 - 1, hxy, gch);
-            pTh0 = tld(p2, z0, hxy, gch);
-            pTh1 = tld(p3, z0 + 1, hxy, gch);
-            hq1 = to_r<R>(h1, tref);
-            hq2 = to_r<R>(h2, tref);
-            L.T[0][hslot] = hq1;
-            L.T[1][hslot] = hq2;
-        }
-        if (djob) {
-            pbd00 = b0[pb0 + hxy]; pbd01 = b1[pb0 + hxy]; pbd02 = b2[pb0 + hxy];
-            pbd10 = b0[pb1 + hxy]; pbd11 = b1[pb1 + hxy]; pbd12 = b2[pb1 + hxy];
-        }
-        if (own) {
-            oq1 = to_r<R>(yq1, tref);
-            oq2 = to_r<R>(yq2, tref);
-            L.T[0][oslot] = oq1;
-            L.T[1][oslot] = oq2;
-        }
-    }
-    __syncthreads();
-
-    for (int k = z0 - 2; k < z1; ++k) {
-        // ---- A: T(k+2) into the ring and the register queues, b(k+1) into the b ring
-        if (own) {
-            yq0 = yq1; yq1 = yq2; yq2 = pTo0;
-            oq0 = oq1; oq1 = oq2; oq2 = to_r<R>(pTo0, tref);
-            L.T[c2][oslot] = oq2;
-            L.B[dn][0][oslot] = pbo00; L.B[dn][1][oslot] = pbo01; L.B[dn][2][oslot] = pbo02;
-            ob00 = ob10; ob01 = ob11; ob02 = ob12;
-            ob10 = pbo00; ob11 = pbo01; ob12 = pbo02;
-        }
-        if (hjob) {
-            hq0 = hq1; hq1 = hq2; hq2 = to_r<R>(pTh0, tref);
-            L.T[c2][hslot] = hq2;
-        }
-        if (djob) { L.B[dn][0][hslot] = pbd00; L.B[dn][1][hslot] = pbd01; L.B[dn][2][hslot] = pbd02; }
-        pTo0 = pTo1; pTh0 = pTh1;
-        pbo00 = pbo10; pbo01 = pbo11; pbo02 = pbo12;
-        pbd00 = pbd10; pbd01 = pbd11; pbd02 = pbd12;
-        // prefetch two planes ahead: T(k+4) and b(k+3), used at plane k+2
-        if (k + 2 < z1) {
-            const double* pt = a.Yin + (size_t)pz4 * plane;
-            const int pbz = oz ? min(k + 3, n2 - 1) : (pz4 == 0 ? n2 - 1 : pz4 - 1);
-            const size_t pb = (size_t)pbz * plane;
+        // prologue (P = 0 at k = z0 - 2): T(z0-2 .. z0+1), b(z0-1), b(z0)
+        {
+            const double* p0 = a.Yin + (size_t)bidx(z0 - 2, n2, oz) * plane;
+            const double* p1 = a.Yin + (size_t)bidx(z0 - 1, n2, oz) * plane;
+            const double* p2 = a.Yin + (size_t)bidx(z0, n2, oz) * plane;
+            const double* p3 = a.Yin + (size_t)bidx(z0 + 1, n2, oz) * plane;
+            const size_t pb0 = (size_t)bidx(z0 - 1, n2, oz) * plane;
+            const size_t pb1 = (size_t)bidx(z0, n2, oz) * plane;
             if (own) {
-                pTo1 = tld(pt, k + 4, oxy, gco);
-                pbo10 = b0[pb + oxy]; pbo11 = b1[pb + oxy]; pbo12 = b2[pb + oxy];
+                tq[0] = tld(p0, z0 - 2, oxy, gco);
+                tq[1] = tld(p1, z0 - 1, oxy, gco);
+                tq[2] = tld(p2, z0, oxy, gco);
+                tq[3] = tld(p3, z0 + 1, oxy, gco);
+                ob[1][0] = b0[pb0 + oxy]; ob[1][1] = b1[pb0 + oxy]; ob[1][2] = b2[pb0 + oxy];
+                ob[2][0] = b0[pb1 + oxy]; ob[2][1] = b1[pb1 + oxy]; ob[2][2] = b2[pb1 + oxy];
             }
-            if (hjob) pTh1 = tld(pt, k + 4, hxy, gch);
-            if (djob) { pbd10 = b0[pb + hxy]; pbd11 = b1[pb + hxy]; pbd12 = b2[pb + hxy]; }
-            pz4 = oz ? min(k + 5, n2 - 1) : (pz4 + 1 == n2 ? 0 : pz4 + 1);
-        }
-        ym2 = q1ym2; y0v = q1y0; my0 = q1my0;
-        q1ym2 = q2ym2; q1y0 = q2y0; q1my0 = q2my0;
-        if (pw && k + 2 >= z0 && k + 2 < z1) {
-            const size_t o = (size_t)(k + 2) * plane + oxy;
-            q2ym2 = a.Ym2[o];
-            q2y0 = a.Y0[o];
-            q2my0 = ((const R*)a.MY0in)[o];
-        }
-
-        // ---- B: slopes of plane k+1.  In-plane neighbours of T(k+1) come from
-        // the ring (written one plane earlier); z neighbours from registers.
-        if (own) {
-            const R* T1 = L.T[c1];
-            const R s0 = cell_slope<R, LIM>(T1[oslot - 1], oq1, T1[oslot + 1], hih0);
-            const R s1 = cell_slope<R, LIM>(T1[oslot - px], oq1, T1[oslot + px], hih1);
-            const R s2 = cell_slope<R, LIM>(oq0, oq1, oq2, hih2);
-            L.S[dn][0][oslot] = s0; L.S[dn][1][oslot] = s1; L.S[dn][2][oslot] = s2;
-            os00 = os10; os01 = os11; os02 = os12;
-            os10 = s0; os11 = s1; os12 = s2;
-        }
-        if (djob) {
-            const R* T1 = L.T[c1];
-            if (dxh) L.S[dn][1][hslot] = cell_slope<R, LIM>(T1[hslot - px], hq1, T1[hslot + px], hih1);
-            else     L.S[dn][0][hslot] = cell_slope<R, LIM>(T1[hslot - 1], hq1, T1[hslot + 1], hih0);
-            L.S[dn][2][hslot] = cell_slope<R, LIM>(hq0, hq1, hq2, hih2);
-        }
-
-        // ---- C: faces of plane k (inputs written in earlier planes; the low
-        // side of the own faces from registers)
-        R fzn = 0;
-        if (k >= z0) {
-            const R* Tk = L.T[c0];
-            const R(*S)[PLMAX] = L.S[dc];
-            const R(*Bv)[PLMAX] = L.B[dc];
-            R* FX = L.FX[fb];
-            R* FY = L.FY[fb];
+            if (hjob) {
+                const double h1 = tld(p0, z0 - 2, hxy, gch), h2 = tld(p1, z0 - 1, hxy, gch);
+                th[0] = tld(p2, z0, hxy, gch);
+                th[1] = tld(p3, z0 + 1, hxy, gch);
+                hq[0] = to_r<R>(h1, tref);
+                hq[1] = to_r<R>(h2, tref);
+                L.T[0][hslot] = hq[0];
+                L.T[1][hslot] = hq[1];
+            }
+            if (djob) {
+                pbd[1][0] = b0[pb0 + hxy]; pbd[1][1] = b1[pb0 + hxy]; pbd[1][2] = b2[pb0 + hxy];
+                pbd[0][0] = b0[pb1 + hxy]; pbd[0][1] = b1[pb1 + hxy]; pbd[0][2] = b2[pb1 + hxy];
+            }
             if (own) {
-                const int r = oslot + 1;
-                FX[ty * (bx + 1) + tx + 1] = face_flux<R, LIM, SAT, KM>(
-                    oq0, Tk[r], ih0, os01, S[1][r], os02, S[2][r],
-                    ob00, ob01, ob02, Bv[0][r], Bv[1][r], Bv[2][r], fk);
-                if (do_y) {
-                    const int u = oslot + px;
-                    FY[(ty + 1) * bx + tx] = face_flux<R, LIM, SAT, KM>(
-                        oq0, Tk[u], ih1, os00, S[0][u], os02, S[2][u],
-                        ob01, ob00, ob02, Bv[1][u], Bv[0][u], Bv[2][u], fk);
-                }
+                oq[0] = to_r<R>(tq[0], tref);
+                oq[1] = to_r<R>(tq[1], tref);
+                L.T[0][oslot] = oq[0];
+                L.T[1][oslot] = oq[1];
             }
-            if (fjob) {
-                // direction-generic gather so that the wave runs one face evaluation
-                const int t1 = fdir == 0 ? 1 : 0;
-                const R f = face_flux<R, LIM, SAT, KM>(
-                    Tk[fL], Tk[fR], fdir == 0 ? ih0 : ih1, S[t1][fL], S[t1][fR], S[2][fL], S[2][fR],
-                    Bv[fdir][fL], Bv[t1][fL], Bv[2][fL], Bv[fdir][fR], Bv[t1][fR], Bv[2][fR], fk);
-                if (fdir == 0) FX[fidx] = f; else FY[fidx] = f;
-            }
-        }
-        if (do_z && own && k >= z0 - 1) {
-            fzn = face_flux<R, LIM, SAT, KM>(oq0, oq1, ih2, os00, os10, os01, os11,
-                                             ob02, ob00, ob01, ob12, ob10, ob11, fk);
         }
         __syncthreads();
 
-        // ---- D: divergence and the stage update of plane k
-        if (k >= z0 && store) {
-            const R* FX = L.FX[fb];
-            const R* FY = L.FY[fb];
-            const int fx = ty * (bx + 1) + tx;
-            R div = (FX[fx + 1] - FX[fx]) * ih0;
-            if (do_y) div = fma(FY[(ty + 1) * bx + tx] - FY[ty * bx + tx], ih1, div);
-            if (do_z) div = fma(fzn - fzp, ih2, div);
-            const size_t o = (size_t)k * plane + oxy;
-            const double tl = a.scale * (double)div;
-            if (a.kind == 0) {
-                a.Yout[o] = tl;
-            } else if (a.kind == 1) {
-                const R m = R(tl);
-                ((R*)a.MY0out)[o] = m;
-                a.Yout[o] = fma(a.mut, (double)m, yq0);
-            } else if (a.kind == 3) {
-                a.Yout[o] = yq0 + tl;
-            } else {
-                a.Yout[o] = stage_combine(a.mu, a.nu, a.omn, a.mut, a.gt, yq0, ym2, y0v, tl, (double)my0);
+        // One plane k with phase P.  LDS rings: temperatures of planes k, k+1,
+        // k+2 in slots r0, r1, r2; slopes and unit vectors of plane k+1 in
+        // slot d0 and of plane k in d1; face buffers in slot d0.
+        auto step = [&](auto ph, int k) __attribute__((always_inline)) {
+            constexpr int P = decltype(ph)::value;
+            constexpr int r0 = P % 3, r1 = (P + 1) % 3, r2 = (P + 2) % 3;   // 3-rings: planes k, k+1, k+2
+            constexpr int d0 = P % 2, d1 = (P + 1) % 2;                     // 2-rings: planes k, k+1
+            constexpr int t0 = r0, t1 = r1, t2 = r2, e0 = d0, e1 = d1;
+            // ---- A: T(k+2) into the ring, b(k+1) into the b ring
+            if (own) {
+                oq[r2] = to_r<R>(tq[(P + 2) % LT], tref);
+                L.T[t2][oslot] = oq[r2];
+                const R* bn = ob[(P + 1) % LB];
+                L.B[e0][0][oslot] = bn[0]; L.B[e0][1][oslot] = bn[1]; L.B[e0][2][oslot] = bn[2];
+            }
+            if (hjob) {
+                hq[r2] = to_r<R>(th[d0], tref);
+                L.T[t2][hslot] = hq[r2];
+            }
+            if (djob) { L.B[e0][0][hslot] = pbd[d1][0]; L.B[e0][1][hslot] = pbd[d1][1]; L.B[e0][2][hslot] = pbd[d1][2]; }
+            // prefetch two planes ahead: T(k+4) and b(k+3), used at plane k+2
+            if (k + 2 < z1) {
+                const double* pt = a.Yin + (size_t)pz4 * plane;
+                const int pbz = oz ? min(k + 3, n2 - 1) : (pz4 == 0 ? n2 - 1 : pz4 - 1);
+                const size_t pb = (size_t)pbz * plane;
+                if (own) {
+                    tq[(P + 4) % LT] = tld(pt, k + 4, oxy, gco);
+                    R* bl = ob[(P + 3) % LB];
+                    bl[0] = b0[pb + oxy]; bl[1] = b1[pb + oxy]; bl[2] = b2[pb + oxy];
+                }
+                if (hjob) th[d0] = tld(pt, k + 4, hxy, gch);
+                if (djob) { pbd[d1][0] = b0[pb + hxy]; pbd[d1][1] = b1[pb + hxy]; pbd[d1][2] = b2[pb + hxy]; }
+                pz4 = oz ? min(k + 5, n2 - 1) : (pz4 + 1 == n2 ? 0 : pz4 + 1);
+            }
+            if (pw && k + 2 >= z0 && k + 2 < z1) {
+                // read once and not again in this launch: streamed past the caches (NT)
+                const size_t o = (size_t)(k + 2) * plane + oxy;
+                if constexpr (NT) {
+                    qym2[r2] = __builtin_nontemporal_load(a.Ym2 + o);
+                    qy0[r2] = __builtin_nontemporal_load(a.Y0 + o);
+                    qmy0[r2] = __builtin_nontemporal_load((const R*)a.MY0in + o);
+                } else {
+                    qym2[r2] = a.Ym2[o];
+                    qy0[r2] = a.Y0[o];
+                    qmy0[r2] = ((const R*)a.MY0in)[o];
+                }
+            }
+
+            // ---- B: slopes of plane k+1.  In-plane neighbours of T(k+1) come from
+            // the ring (written one plane earlier); z neighbours from registers.
+            if (own) {
+                const R* T1 = L.T[t1];
+                const R s0 = cell_slope<R, LIM>(T1[oslot - 1], oq[r1], T1[oslot + 1], hih0);
+                const R s1 = cell_slope<R, LIM>(T1[oslot - px], oq[r1], T1[oslot + px], hih1);
+                const R s2 = cell_slope<R, LIM>(oq[r0], oq[r1], oq[r2], hih2);
+                L.S[e0][0][oslot] = s0; L.S[e0][1][oslot] = s1; L.S[e0][2][oslot] = s2;
+                os[d1][0] = s0; os[d1][1] = s1; os[d1][2] = s2;
+            }
+            if (djob) {
+                const R* T1 = L.T[t1];
+                if (dxh) L.S[e0][1][hslot] = cell_slope<R, LIM>(T1[hslot - px], hq[r1], T1[hslot + px], hih1);
+                else     L.S[e0][0][hslot] = cell_slope<R, LIM>(T1[hslot - 1], hq[r1], T1[hslot + 1], hih0);
+                L.S[e0][2][hslot] = cell_slope<R, LIM>(hq[r0], hq[r1], hq[r2], hih2);
+            }
+
+            // ---- C: faces of plane k (inputs written in earlier planes; the low
+            // side of the own faces from registers)
+            const R* ob0 = ob[P % LB];         // b(k)
+            const R* ob1 = ob[(P + 1) % LB];   // b(k+1)
+            if (k >= z0) {
+                const R* Tk = L.T[t0];
+                const R(*S)[PLMAX] = L.S[e1];
+                const R(*Bv)[PLMAX] = L.B[e1];
+                R* FX = L.FX[e0];
+                R* FY = L.FY[e0];
+                if (own) {
+                    const int r = oslot + 1;
+                    FX[ty * (bx + 1) + tx + 1] = face_flux<R, LIM, SAT, KM>(
+                        oq[r0], Tk[r], ih0, os[d0][1], S[1][r], os[d0][2], S[2][r],
+                        ob0[0], ob0[1], ob0[2], Bv[0][r], Bv[1][r], Bv[2][r], fk);
+                    if (do_y) {
+                        const int u = oslot + px;
+                        FY[(ty + 1) * bx + tx] = face_flux<R, LIM, SAT, KM>(
+                            oq[r0], Tk[u], ih1, os[d0][0], S[0][u], os[d0][2], S[2][u],
+                            ob0[1], ob0[0], ob0[2], Bv[1][u], Bv[0][u], Bv[2][u], fk);
+                    }
+                }
+                if (fjob) {
+                    // direction-generic gather so that the wave runs one face evaluation
+                    const int u1 = fdir == 0 ? 1 : 0;
+                    const R f = face_flux<R, LIM, SAT, KM>(
+                        Tk[fL], Tk[fR], fdir == 0 ? ih0 : ih1, S[u1][fL], S[u1][fR], S[2][fL], S[2][fR],
+                        Bv[fdir][fL], Bv[u1][fL], Bv[2][fL], Bv[fdir][fR], Bv[u1][fR], Bv[2][fR], fk);
+                    if (fdir == 0) FX[fidx] = f; else FY[fidx] = f;
+                }
+            }
+            zf[d0] = 0;
+            if (do_z && own && k >= z0 - 1) {
+                zf[d0] = face_flux<R, LIM, SAT, KM>(oq[r0], oq[r1], ih2, os[d0][0], os[d1][0], os[d0][1], os[d1][1],
+                                                    ob0[2], ob0[0], ob0[1], ob1[2], ob1[0], ob1[1], fk);
+            }
+            __syncthreads();
+
+            // ---- D: divergence and the stage update of plane k
+            if (k >= z0 && store) {
+                const R* FX = L.FX[e0];
+                const R* FY = L.FY[e0];
+                const int fx = ty * (bx + 1) + tx;
+                R div = (FX[fx + 1] - FX[fx]) * ih0;
+                if (do_y) div = fma(FY[(ty + 1) * bx + tx] - FY[ty * bx + tx], ih1, div);
+                if (do_z) div = fma(zf[d0] - zf[d1], ih2, div);
+                const size_t o = (size_t)k * plane + oxy;
+                const double tl = a.scale * (double)div;
+                const double yk = tq[P % LT];
+                if (a.kind == 0) {
+                    a.Yout[o] = tl;
+                } else if (a.kind == 1) {
+                    const R m = R(tl);
+                    ((R*)a.MY0out)[o] = m;
+                    a.Yout[o] = fma(a.mut, (double)m, yk);
+                } else if (a.kind == 3) {
+                    a.Yout[o] = yk + tl;
+                } else {
+                    const double y = stage_combine(a.mu, a.nu, a.omn, a.mut, a.gt, yk, qym2[r0], qy0[r0], tl,
+                                                   (double)qmy0[r0]);
+                    if constexpr (NT) __builtin_nontemporal_store(y, a.Yout + o);
+                    else a.Yout[o] = y;
+                }
+            }
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        using I4 = std::integral_constant<int, 4>;
+        using I5 = std::integral_constant<int, 5>;
+        int k = z0 - 2;
+        for (; k + 5 < z1; k += 6) {
+            step(I0{}, k);
+            step(I1{}, k + 1);
+            step(I2{}, k + 2);
+            step(I3{}, k + 3);
+            step(I4{}, k + 4);
+            step(I5{}, k + 5);
+        }
+        if (k < z1) step(I0{}, k);
+        if (k + 1 < z1) step(I1{}, k + 1);
+        if (k + 2 < z1) step(I2{}, k + 2);
+        if (k + 3 < z1) step(I3{}, k + 3);
+        if (k + 4 < z1) step(I4{}, k + 4);
+    } else {
+        static_assert(UNR == 1, "the plane loop runs unrolled six-fold or not at all");
+        // Prefetch pipeline, two planes deep: set 0 is stored into LDS at this
+        // plane's step A, set 1 at the next plane's.  Values stay in their loaded
+        // type until they are used, so that no conversion forces an early wait.
+        double pTo0 = 0.0, pTo1 = 0.0;            // T(k+2), T(k+3): own cell
+        double pTh0 = 0.0, pTh1 = 0.0;            // T(k+2), T(k+3): halo cell
+        R pbo00 = 0, pbo01 = 0, pbo02 = 0, pbo10 = 0, pbo11 = 0, pbo12 = 0;   // b(k+1), b(k+2): own
+        R pbd00 = 0, pbd01 = 0, pbd02 = 0, pbd10 = 0, pbd11 = 0, pbd12 = 0;   // b(k+1), b(k+2): halo
+        double yq0 = 0.0, yq1 = 0.0, yq2 = 0.0;   // own FP64 input, planes k, k+1, k+2
+        R oq0 = 0, oq1 = 0, oq2 = 0;              // same in flux precision
+        R hq0 = 0, hq1 = 0, hq2 = 0;              // halo cell input, planes k, k+1, k+2
+        R ob00 = 0, ob01 = 0, ob02 = 0;           // own b, plane k
+        R ob10 = 0, ob11 = 0, ob12 = 0;           // own b, plane k+1
+        R os00 = 0, os01 = 0, os02 = 0;           // own slopes, plane k
+        R os10 = 0, os11 = 0, os12 = 0;           // own slopes, plane k+1
+        R fzp = 0;                                // +z face flux of plane k-1
+        // pointwise stage inputs Y_{j-2}, Y0, tau M(Y0): plane k (cur), k+1 (q1),
+        // k+2 (q2), loaded two planes ahead
+        double ym2 = 0.0, y0v = 0.0;
+        R my0 = 0;
+        double q1ym2 = 0.0, q1y0 = 0.0, q2ym2 = 0.0, q2y0 = 0.0;
+        R q1my0 = 0, q2my0 = 0;
+        const bool pw = own && a.kind == 2;
+
+        // ring slots: T(k) c0, T(k+1) c1, T(k+2) c2; slopes/b of plane k in dc, of k+1 in dn
+        int c0 = 0, c1 = 1, c2 = 2, dc = 1, dn = 0, fb = 0;
+        {
+            const double* p0 = a.Yin + (size_t)bidx(z0 - 2, n2, oz) * plane;
+            const double* p1 = a.Yin + (size_t)bidx(z0 - 1, n2, oz) * plane;
+            const double* p2 = a.Yin + (size_t)bidx(z0, n2, oz) * plane;
+            const double* p3 = a.Yin + (size_t)bidx(z0 + 1, n2, oz) * plane;
+            const size_t pb0 = (size_t)bidx(z0 - 1, n2, oz) * plane;
+            const size_t pb1 = (size_t)bidx(z0, n2, oz) * plane;
+            if (own) {
+                yq1 = tld(p0, z0 - 2, oxy, gco);
+                yq2 = tld(p1, z0 - 1, oxy, gco);
+                pTo0 = tld(p2, z0, oxy, gco);
+                pTo1 = tld(p3, z0 + 1, oxy, gco);
+                pbo00 = b0[pb0 + oxy]; pbo01 = b1[pb0 + oxy]; pbo02 = b2[pb0 + oxy];
+                pbo10 = b0[pb1 + oxy]; pbo11 = b1[pb1 + oxy]; pbo12 = b2[pb1 + oxy];
+            }
+            if (hjob) {
+                const double h1 = tld(p0, z0 - 2, hxy, gch), h2 = tld(p1, z0 - 1, hxy, gch);
+                pTh0 = tld(p2, z0, hxy, gch);
+                pTh1 = tld(p3, z0 + 1, hxy, gch);
+                hq1 = to_r<R>(h1, tref);
+                hq2 = to_r<R>(h2, tref);
+                L.T[0][hslot] = hq1;
+                L.T[1][hslot] = hq2;
+            }
+            if (djob) {
+                pbd00 = b0[pb0 + hxy]; pbd01 = b1[pb0 + hxy]; pbd02 = b2[pb0 + hxy];
+                pbd10 = b0[pb1 + hxy]; pbd11 = b1[pb1 + hxy]; pbd12 = b2[pb1 + hxy];
+            }
+            if (own) {
+                oq1 = to_r<R>(yq1, tref);
+                oq2 = to_r<R>(yq2, tref);
+                L.T[0][oslot] = oq1;
+                L.T[1][oslot] = oq2;
             }
         }
-        fzp = fzn;
-        const int t = c0; c0 = c1; c1 = c2; c2 = t;
-        const int d = dc; dc = dn; dn = d;
-        fb ^= 1;
+        __syncthreads();
+
+        for (int k = z0 - 2; k < z1; ++k) {
+            // ---- A: T(k+2) into the ring and the register queues, b(k+1) into the b ring
+            if (own) {
+                yq0 = yq1; yq1 = yq2; yq2 = pTo0;
+                oq0 = oq1; oq1 = oq2; oq2 = to_r<R>(pTo0, tref);
+                L.T[c2][oslot] = oq2;
+                L.B[dn][0][oslot] = pbo00; L.B[dn][1][oslot] = pbo01; L.B[dn][2][oslot] = pbo02;
+                ob00 = ob10; ob01 = ob11; ob02 = ob12;
+                ob10 = pbo00; ob11 = pbo01; ob12 = pbo02;
+            }
+            if (hjob) {
+                hq0 = hq1; hq1 = hq2; hq2 = to_r<R>(pTh0, tref);
+                L.T[c2][hslot] = hq2;
+            }
+            if (djob) { L.B[dn][0][hslot] = pbd00; L.B[dn][1][hslot] = pbd01; L.B[dn][2][hslot] = pbd02; }
+            pTo0 = pTo1; pTh0 = pTh1;
+            pbo00 = pbo10; pbo01 = pbo11; pbo02 = pbo12;
+            pbd00 = pbd10; pbd01 = pbd11; pbd02 = pbd12;
+            // prefetch two planes ahead: T(k+4) and b(k+3), used at plane k+2
+            if (k + 2 < z1) {
+                const double* pt = a.Yin + (size_t)pz4 * plane;
+                const int pbz = oz ? min(k + 3, n2 - 1) : (pz4 == 0 ? n2 - 1 : pz4 - 1);
+                const size_t pb = (size_t)pbz * plane;
+                if (own) {
+                    pTo1 = tld(pt, k + 4, oxy, gco);
+                    pbo10 = b0[pb + oxy]; pbo11 = b1[pb + oxy]; pbo12 = b2[pb + oxy];
+                }
+                if (hjob) pTh1 = tld(pt, k + 4, hxy, gch);
+                if (djob) { pbd10 = b0[pb + hxy]; pbd11 = b1[pb + hxy]; pbd12 = b2[pb + hxy]; }
+                pz4 = oz ? min(k + 5, n2 - 1) : (pz4 + 1 == n2 ? 0 : pz4 + 1);
+            }
+            ym2 = q1ym2; y0v = q1y0; my0 = q1my0;
+            q1ym2 = q2ym2; q1y0 = q2y0; q1my0 = q2my0;
+            if (pw && k + 2 >= z0 && k + 2 < z1) {
+                const size_t o = (size_t)(k + 2) * plane + oxy;
+                q2ym2 = a.Ym2[o];
+                q2y0 = a.Y0[o];
+                q2my0 = ((const R*)a.MY0in)[o];
+            }
+
+            // ---- B: slopes of plane k+1.  In-plane neighbours of T(k+1) come from
+            // the ring (written one plane earlier); z neighbours from registers.
+            if (own) {
+                const R* T1 = L.T[c1];
+                const R s0 = cell_slope<R, LIM>(T1[oslot - 1], oq1, T1[oslot + 1], hih0);
+                const R s1 = cell_slope<R, LIM>(T1[oslot - px], oq1, T1[oslot + px], hih1);
+                const R s2 = cell_slope<R, LIM>(oq0, oq1, oq2, hih2);
+                L.S[dn][0][oslot] = s0; L.S[dn][1][oslot] = s1; L.S[dn][2][oslot] = s2;
+                os00 = os10; os01 = os11; os02 = os12;
+                os10 = s0; os11 = s1; os12 = s2;
+            }
+            if (djob) {
+                const R* T1 = L.T[c1];
+                if (dxh) L.S[dn][1][hslot] = cell_slope<R, LIM>(T1[hslot - px], hq1, T1[hslot + px], hih1);
+                else     L.S[dn][0][hslot] = cell_slope<R, LIM>(T1[hslot - 1], hq1, T1[hslot + 1], hih0);
+                L.S[dn][2][hslot] = cell_slope<R, LIM>(hq0, hq1, hq2, hih2);
+            }
+
+            // ---- C: faces of plane k (inputs written in earlier planes; the low
+            // side of the own faces from registers)
+            R fzn = 0;
+            if (k >= z0) {
+                const R* Tk = L.T[c0];
+                const R(*S)[PLMAX] = L.S[dc];
+                const R(*Bv)[PLMAX] = L.B[dc];
+                R* FX = L.FX[fb];
+                R* FY = L.FY[fb];
+                if (own) {
+                    const int r = oslot + 1;
+                    FX[ty * (bx + 1) + tx + 1] = face_flux<R, LIM, SAT, KM>(
+                        oq0, Tk[r], ih0, os01, S[1][r], os02, S[2][r],
+                        ob00, ob01, ob02, Bv[0][r], Bv[1][r], Bv[2][r], fk);
+                    if (do_y) {
+                        const int u = oslot + px;
+                        FY[(ty + 1) * bx + tx] = face_flux<R, LIM, SAT, KM>(
+                            oq0, Tk[u], ih1, os00, S[0][u], os02, S[2][u],
+                            ob01, ob00, ob02, Bv[1][u], Bv[0][u], Bv[2][u], fk);
+                    }
+                }
+                if (fjob) {
+                    // direction-generic gather so that the wave runs one face evaluation
+                    const int t1 = fdir == 0 ? 1 : 0;
+                    const R f = face_flux<R, LIM, SAT, KM>(
+                        Tk[fL], Tk[fR], fdir == 0 ? ih0 : ih1, S[t1][fL], S[t1][fR], S[2][fL], S[2][fR],
+                        Bv[fdir][fL], Bv[t1][fL], Bv[2][fL], Bv[fdir][fR], Bv[t1][fR], Bv[2][fR], fk);
+                    if (fdir == 0) FX[fidx] = f; else FY[fidx] = f;
+                }
+            }
+            if (do_z && own && k >= z0 - 1) {
+                fzn = face_flux<R, LIM, SAT, KM>(oq0, oq1, ih2, os00, os10, os01, os11,
+                                                 ob02, ob00, ob01, ob12, ob10, ob11, fk);
+            }
+            __syncthreads();
+
+            // ---- D: divergence and the stage update of plane k
+            if (k >= z0 && store) {
+                const R* FX = L.FX[fb];
+                const R* FY = L.FY[fb];
+                const int fx = ty * (bx + 1) + tx;
+                R div = (FX[fx + 1] - FX[fx]) * ih0;
+                if (do_y) div = fma(FY[(ty + 1) * bx + tx] - FY[ty * bx + tx], ih1, div);
+                if (do_z) div = fma(fzn - fzp, ih2, div);
+                const size_t o = (size_t)k * plane + oxy;
+                const double tl = a.scale * (double)div;
+                if (a.kind == 0) {
+                    a.Yout[o] = tl;
+                } else if (a.kind == 1) {
+                    const R m = R(tl);
+                    ((R*)a.MY0out)[o] = m;
+                    a.Yout[o] = fma(a.mut, (double)m, yq0);
+                } else if (a.kind == 3) {
+                    a.Yout[o] = yq0 + tl;
+                } else {
+                    a.Yout[o] = stage_combine(a.mu, a.nu, a.omn, a.mut, a.gt, yq0, ym2, y0v, tl, (double)my0);
+                }
+            }
+            fzp = fzn;
+            const int t = c0; c0 = c1; c1 = c2; c2 = t;
+            const int d = dc; dc = dn; dn = d;
+            fb ^= 1;
+        }
     }
 }
 
