@@ -627,10 +627,13 @@ def horizon_errors_from_tests():
         return None
 
 
-def run_grid(torch, rkl, w, T0, b, precision, steps, warmup, variant=-1, one_stage_only=False):
+def run_grid(torch, rkl, w, T0, b, precision, steps, warmup, variant=-1, one_stage_only=False, chain=False):
     """One timed single-grid run: plan, variant (autotuned unless given),
     `warmup` untimed and `steps` timed super-steps from T0, the dominant
-    kernel's launches timed with HIP events.  Returns a dict."""
+    kernel's launches timed with HIP events.  Returns a dict.  chain: also
+    time the same super-steps as one rkl_supersteps_async call (each
+    super-step after the first takes its extrema from the previous one's
+    last stage) and check that it gives the same bits."""
     plan = rkl.Plan([rkl.grid_desc(w.n, w.h, ndim=3, **w.params)], precision=precision)
     T = T0.clone()
     dt = w.ratio * plan.dt_par(T)     # the library's own dt_par of the initial field
@@ -658,6 +661,24 @@ def run_grid(torch, rkl, w, T0, b, precision, steps, warmup, variant=-1, one_sta
     sec = time.perf_counter() - t0
     ms, launches, cell_stages = rkl.rkl_profile_read(plan.handle, fuse)
     rkl.rkl_profile(plan.handle, 0)
+    chained = None
+    if chain and fuse == 1:
+        s_cap = max(per_step) + 1
+        s_out = torch.zeros(steps, dtype=torch.int32, device=T.device)
+        T2 = T0.clone()
+        plan.supersteps_async(T2, b, dt, steps, s_cap, s_out=s_out)   # untimed
+        T2.copy_(T0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.supersteps_async(T2, b, dt, steps, s_cap, s_out=s_out)
+        torch.cuda.synchronize()
+        sec2 = time.perf_counter() - t0
+        ss = [int(v) for v in s_out.cpu().tolist()]
+        chained = {"value": w.cells * sum(ss) / sec2, "ms_per_step": sec2 * 1e3 / steps, "s_cap": s_cap,
+                   "stages_per_step": ss, "same_bits_as_rkl_superstep": bool(torch.equal(T, T2)),
+                   "entry": "rkl_supersteps_async (one call, the extrema of each super-step's start from "
+                            "the previous super-step's last stage)"}
+        del T2
     plan.close()
     del T
     bpc = bytes_per_cell_stage(precision, fuse)
@@ -667,7 +688,7 @@ def run_grid(torch, rkl, w, T0, b, precision, steps, warmup, variant=-1, one_sta
             "dt_hyp": dt, "variant": variant, "tile": list(tile[:3]), "stages_per_launch": fuse,
             "autotuned_ms_per_step": tuned_ms, "kernel": "%s (stages j>=2)" % KERNEL_NAMES[fuse],
             "bytes_per_cell_stage": bpc, "avg_launch_ms": avg * 1e3, "launches": launches,
-            "achieved": achieved, "kernel_cell_stage_per_s": cell_stages / (ms / 1e3)}
+            "achieved": achieved, "kernel_cell_stage_per_s": cell_stages / (ms / 1e3), "chained": chained}
 
 
 def batched_leg(torch, inputs, rkl, workload, steps, warmup):
@@ -744,7 +765,8 @@ def main():
     if precision == "mixed" and (args.no_legs or args.workload != "fused_768"):
         del b64
         b64 = None
-    r = run_grid(torch, rkl, w, T0, bdev, precision, args.steps, args.warmup, args.variant)
+    r = run_grid(torch, rkl, w, T0, bdev, precision, args.steps, args.warmup, args.variant,
+                 chain=args.workload == "fused_768" and not args.no_legs)
     del bdev
     torch.cuda.empty_cache()
     traffic = traffic_for(args.workload, precision, r["stages_per_launch"], r["variant"])
@@ -791,6 +813,8 @@ def main():
         legs["fp64_plain_768"]["frac"] = f["achieved"] / PEAK_HBM_GBS
         legs["fp64_plain_768"]["dt_hyp_same"] = f["dt_hyp"] == r["dt_hyp"]
         legs["mixed_over_fp64_768"] = r["value"] / f["value"]
+        if r["chained"]:
+            legs["supersteps_async_768"] = r["chained"]
         del T0
         torch.cuda.empty_cache()
         legs["patches_2000_mixed_batched"] = batched_leg(torch, inputs, rkl, "patches_2000", 10, 2)

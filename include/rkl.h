@@ -224,6 +224,27 @@ rkl_status rkl_superstep_async(rkl_plan_t plan, int32_t grid, double *T, const v
                                int32_t s_cap, int32_t *s_out, void *stream);
 
 /*
+ * rkl_supersteps_async: nsteps super-steps of rkl_superstep_async (Appendix A,
+ * Eq. rkl2scheme; s from Eq. RKL-s) one after another on the same T, b and
+ * dt_hyp, enqueued with no host synchronisation and no allocation.  Each
+ * super-step needs the extrema of its starting T for dt_par and the FP32
+ * reference temperature (Sec. 3.1, Eq. dt_exp).  On 3-D grids without fixed
+ * axes the last stage of each super-step keeps the extrema of the T it
+ * writes, so every super-step after the first skips the reduction pass over
+ * T (a read of the whole field); other grids take the pass each time.  The
+ * extrema are the same numbers either way, so the results have the same
+ * bits as nsteps calls of rkl_superstep_async.  s_out: device int32 array
+ * of nsteps entries (may be NULL) receiving each super-step's s; a
+ * super-step with s > s_cap leaves T unchanged and is flagged
+ * RKL_FLAG_STAGES (rkl_query), and the next one takes the reduction pass.
+ * nsteps >= 1 and s_cap in [2, the plan's smax] (RKL_EINVAL otherwise);
+ * RKL2 plans only.  T must not change outside these launches while they
+ * run.
+ */
+rkl_status rkl_supersteps_async(rkl_plan_t plan, int32_t grid, double *T, const void *b, double dt_hyp,
+                                int32_t nsteps, int32_t s_cap, int32_t *s_out, void *stream);
+
+/*
  * rkl_superstep_noalloc: for callers that cannot allocate device memory --
  * code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  The super-step of rkl_superstep_async (RKL2, s on the device,

@@ -49,6 +49,8 @@ struct rkl_plan_s {
     double* coef = nullptr;     // RKL2 table, device
     GridState* state = nullptr; // ngrids entries, device
     double* partials = nullptr; // 3 x 1024 doubles
+    double* ext_part = nullptr; // 3 per workgroup of a one-stage launch, the largest over grids and variants
+    int32_t* ext_ok = nullptr;  // ngrids flags: ext_part holds the extrema of the grid's T
     int32_t* s_dev = nullptr;   // scratch for the stage-count read-back
     int32_t* s_host = nullptr;  // pinned
     BatchPlan* batch = nullptr; // batched launch data (rkl_batch.hip)
@@ -182,6 +184,8 @@ static void free_plan(rkl_plan_s* p) {
     (void)hipFree(p->coef);
     (void)hipFree(p->state);
     (void)hipFree(p->partials);
+    (void)hipFree(p->ext_part);
+    (void)hipFree(p->ext_ok);
     (void)hipFree(p->s_dev);
     if (p->s_host) (void)hipHostFree(p->s_host);
     delete p;
@@ -435,12 +439,18 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
 
     const size_t rs = o.precision == RKL_MIXED ? sizeof(float) : sizeof(double);
     const std::vector<double> tab = coefficient_table(o.smax, o.scheme);
+    int64_t ext_blocks = 1;
+    for (int32_t g = 0; g < ngrids; ++g)
+        for (int v = 0; v < variant_count(); ++v)
+            if (variant_get(v).fuse == 1) ext_blocks = std::max(ext_blocks, stage_blocks(variant_get(v), p->gc[g]));
     bool ok = hipMalloc(&p->Ya, sizeof(double) * p->total) == hipSuccess &&
               hipMalloc(&p->Yb, sizeof(double) * p->total) == hipSuccess &&
               hipMalloc(&p->MY0, rs * p->total) == hipSuccess &&
               hipMalloc(&p->coef, sizeof(double) * tab.size()) == hipSuccess &&
               hipMalloc(&p->state, sizeof(GridState) * ngrids) == hipSuccess &&
               hipMalloc(&p->partials, sizeof(double) * 3 * 1024) == hipSuccess &&
+              hipMalloc(&p->ext_part, sizeof(double) * 3 * ext_blocks) == hipSuccess &&
+              hipMalloc(&p->ext_ok, sizeof(int32_t) * ngrids) == hipSuccess &&
               hipMalloc(&p->s_dev, sizeof(int32_t)) == hipSuccess &&
               hipHostMalloc((void**)&p->s_host, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
@@ -450,6 +460,7 @@ rkl_status rkl_plan(const rkl_grid_desc* grids, int32_t ngrids, const rkl_option
     }
     e = hipMemcpy(p->coef, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->state, 0, sizeof(GridState) * ngrids);
+    if (e == hipSuccess) e = hipMemset(p->ext_ok, 0, sizeof(int32_t) * ngrids);
     // the set-up above is ordered on the legacy stream; finish it so that the
     // caller's first launch on any stream sees it
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -661,6 +672,49 @@ rkl_status rkl_superstep_async(rkl_plan_t p, int32_t g, double* T, const void* b
         HIPCHECK(launch_stage(p->precision, v, gc, j == 1 ? 1 : 2, j, nullptr, nullptr, nullptr, M, M, T, b,
                               p->state + g, p->coef, s, 0.0, &r),
                  "routed stage launch");
+    return RKL_OK;
+}
+
+rkl_status rkl_supersteps_async(rkl_plan_t p, int32_t g, double* T, const void* b, double dt_hyp,
+                                int32_t nsteps, int32_t s_cap, int32_t* s_out, void* stream) {
+    rkl_status st = check_grid(p, g);
+    if (st != RKL_OK) return st;
+    if ((st = check_ghosts(p, g)) != RKL_OK) return st;
+    if (!T || !b) return fail(RKL_EINVAL, "NULL field pointer");
+    if ((const void*)T == b) return fail(RKL_EINVAL, "b must not alias T");
+    if (!(dt_hyp >= 0.0) || !std::isfinite(dt_hyp)) return fail(RKL_EINVAL, "dt_hyp must be finite and >= 0");
+    if (p->scheme != RKL_RKL2) return fail(RKL_EINVAL, "rkl_supersteps_async implements RKL2 only");
+    if (s_cap < 2 || s_cap > p->smax)
+        return fail(RKL_EINVAL, "s_cap must be in [2, smax=" + std::to_string(p->smax) + "]");
+    if (nsteps < 1) return fail(RKL_EINVAL, "nsteps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const GridConst& gc = p->gc[g];
+    Variant v = variant_get(p->variant);
+    if (v.fuse != 1) v = variant_get(0);   // routed launches are one stage each
+    // the compile-time-shaped stage kernels keep the last stage's extrema;
+    // other grids take the reduction pass before every super-step
+    const bool keep = gc.ndim == 3 && !gc.fixed;
+    const int64_t N = p->off[g + 1] - p->off[g];
+    const int nb = reduce_blocks(N);
+    const int64_t nbx = stage_blocks(v, gc);
+    const size_t rs = p->precision == RKL_MIXED ? sizeof(float) : sizeof(double);
+    void* M = (char*)p->MY0 + rs * p->off[g];
+    const Route r{p->Ya + p->off[g], p->Yb + p->off[g], s_cap, 0};
+    const ExtOut ext{p->ext_part, p->ext_ok + g};
+    for (int32_t i = 0; i < nsteps; ++i) {
+        // super-step 0 always reduces (and clears the flag); later ones skip the
+        // pass when the previous super-step's last stage left the extrema
+        const bool chain = keep && i > 0;
+        HIPCHECK(launch_reduce(T, N, p->partials, nb, s, chain ? p->ext_ok + g : nullptr), "reduce launch");
+        HIPCHECK(launch_finalize(p->partials, nb, gc, dt_hyp, 0, p->state + g, s_out ? s_out + i : nullptr, s_cap,
+                                 s, nullptr, chain ? p->ext_part : nullptr, chain ? (int)nbx : 0,
+                                 keep ? p->ext_ok + g : nullptr),
+                 "finalize launch");
+        for (int j = 1; j <= s_cap; ++j)
+            HIPCHECK(launch_stage(p->precision, v, gc, j == 1 ? 1 : 2, j, nullptr, nullptr, nullptr, M, M, T, b,
+                                  p->state + g, p->coef, s, 0.0, &r, keep && j >= 2 ? &ext : nullptr),
+                     "routed stage launch");
+    }
     return RKL_OK;
 }
 

@@ -169,6 +169,7 @@ __device__ __forceinline__ void batch_tile(const BatchBufs& P, int g, int j, int
     a.ndim = G.gc.ndim;
     a.bc = G.gc.bc;
     a.fixed = 0;         // batched plans take no fixed axes
+    a.ext = 0;
     for (int i = 0; i < 6; ++i) a.gh[i] = nullptr;
     a.bx = G.bx;
     a.by = G.by;

@@ -117,14 +117,22 @@ int variant_count();
 Variant variant_get(int v);
 
 // Launchers (enqueue only; return the HIP error of the launch).
-hipError_t launch_reduce(const double* T, int64_t N, double* partials, int nblocks, hipStream_t st);
+// skip (may be NULL): when *skip is nonzero on the device the launch does
+// nothing (the extrema come from the previous super-step's last stage).
+hipError_t launch_reduce(const double* T, int64_t N, double* partials, int nblocks, hipStream_t st,
+                         const int32_t* skip = nullptr);
 int reduce_blocks(int64_t N);
 // coef_rows (may be NULL): for a super-step (mode 0, RKL2) whose stage count
 // s is in [2, smax], rows 0..s of its coefficient table (rkl2_row, 5 doubles
 // each; room for smax + 1 rows) are written there on the device.
+// ext_ok (may be NULL): when *ext_ok is nonzero on the device and ext_part
+// is given, the extrema are taken from ext_part (ext_nb per-workgroup
+// triples written by the last stage of the previous super-step) instead of
+// `partials`; *ext_ok is cleared either way.
 hipError_t launch_finalize(const double* partials, int nblocks, const GridConst& gc, double dt_hyp,
                            int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st,
-                           double* coef_rows = nullptr);
+                           double* coef_rows = nullptr, const double* ext_part = nullptr, int ext_nb = 0,
+                           int32_t* ext_ok = nullptr);
 // Device-side routing of an RKL2 stage (for launch sequences that do not
 // know s on the host): with s the grid's device-side stage count, stage j
 // does nothing when j > s or s is outside [2, s_cap]; otherwise it reads
@@ -138,6 +146,17 @@ struct Route {
     int s_cap;
     int coef_flat;
 };
+// Extrema of the last stage (routed sequences, 3-D grids without fixed axes):
+// the launch of stage j = s writes, per workgroup, the maximum, the minimum
+// and a non-finite flag of the Y_s it stores to part[3 w .. 3 w + 2] (w the
+// workgroup index) and sets *ok = 1, for the next super-step's finalize
+// (the dt_par bound and T_ref of Sec. 3.1 Eq. dt_exp need only these).
+struct ExtOut {
+    double* part;
+    int32_t* ok;
+};
+// workgroups of a one-stage launch of variant v on grid gc
+int64_t stage_blocks(Variant v, const GridConst& gc);
 // kind: 0 flux divergence into Yout, 1 first stage, 2 stage j >= 2,
 // 3 explicit sub-step Yout = Yin + tau L(Yin) with sub_scale = -tau (gamma-1)/rho.
 // With `route` set (kinds 1 and 2), Yin, Ym2 and Yout are chosen on the
@@ -146,7 +165,7 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
                         const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
                         const double* coef, hipStream_t st, double sub_scale = 0.0,
-                        const Route* route = nullptr);
+                        const Route* route = nullptr, const ExtOut* ext = nullptr);
 // stages j..j+F-1 (F = v.fuse in 2..4, 2 <= j, j+F-1 < s) in one launch,
 // RKL_MIXED and periodic 3-D grids only; Ya receives Y_{j+F-2}, Yb Y_{j+F-1};
 // they must alias none of Yin, Ym2, Y0

@@ -24,7 +24,9 @@ Variant variant_get(int v) { return kVariants[v]; }
 // ----------------------------------------------------------- reduction ----
 // per-block maximum, minimum and a non-finite flag of T
 __global__ __launch_bounds__(256) void reduce_minmax_kernel(const double* __restrict__ T, int64_t N,
-                                                            double* __restrict__ part) {
+                                                            double* __restrict__ part,
+                                                            const int32_t* __restrict__ skip) {
+    if (skip && *skip) return;   // uniform: the extrema are already there
     double mx = -INFINITY, mn = INFINITY, bad = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
         const double v = T[i];
@@ -60,20 +62,32 @@ int reduce_blocks(int64_t N) {
     return (int)b;
 }
 
-hipError_t launch_reduce(const double* T, int64_t N, double* partials, int nblocks, hipStream_t st) {
-    reduce_minmax_kernel<<<nblocks, 256, 0, st>>>(T, N, partials);
+hipError_t launch_reduce(const double* T, int64_t N, double* partials, int nblocks, hipStream_t st,
+                         const int32_t* skip) {
+    reduce_minmax_kernel<<<nblocks, 256, 0, st>>>(T, N, partials, skip);
     return hipGetLastError();
 }
 
 // mode 0: super-step (computes s); mode 1: flux_div / dt_par only (s = 0).
-// Every lane ends the butterfly with the grid's extrema, so all 64 lanes
-// form the same state; lane 0 stores it and the lanes share the rows of the
-// coefficient table (coef_rows, RKL2 super-steps with 2 <= s <= smax).
-__global__ __launch_bounds__(64) void finalize_kernel(const double* __restrict__ part, int nb, GridConst g,
-                                                      double dt_hyp, int mode, GridState* st,
-                                                      int32_t* s_out, int smax, double* coef_rows) {
+// Four waves read the partial extrema; every lane of wave 0 then holds the
+// grid's extrema and forms the same state; lane 0 stores it and the lanes
+// of wave 0 share the rows of the coefficient table (coef_rows, RKL2
+// super-steps with 2 <= s <= smax).
+constexpr int kFinThreads = 256;
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(const double* __restrict__ part, int nb, GridConst g,
+                                                               double dt_hyp, int mode, GridState* st,
+                                                               int32_t* s_out, int smax, double* coef_rows,
+                                                               const double* __restrict__ ext_part, int ext_nb,
+                                                               int32_t* ext_ok) {
+    if (ext_ok) {
+        const bool use = ext_part && *ext_ok;   // the same in every lane
+        if (use) {
+            part = ext_part;
+            nb = ext_nb;
+        }
+    }
     double mx = -INFINITY, mn = INFINITY, bad = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 64) {
+    for (int i = threadIdx.x; i < nb; i += kFinThreads) {
         mx = fmax(mx, part[3 * i]);
         mn = fmin(mn, part[3 * i + 1]);
         bad = fmax(bad, part[3 * i + 2]);
@@ -83,23 +97,39 @@ __global__ __launch_bounds__(64) void finalize_kernel(const double* __restrict__
         mn = fmin(mn, __shfl_xor(mn, off));
         bad = fmax(bad, __shfl_xor(bad, off));
     }
+    __shared__ double sm[3][kFinThreads / 64];
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    if (l == 0) {
+        sm[0][w] = mx;
+        sm[1][w] = mn;
+        sm[2][w] = bad;
+    }
+    __syncthreads();   // also orders every lane's read of *ext_ok before its clearing below
+    if (w != 0) return;
+    for (int i = 1; i < kFinThreads / 64; ++i) {
+        mx = fmax(mx, sm[0][i]);
+        mn = fmin(mn, sm[1][i]);
+        bad = fmax(bad, sm[2][i]);
+    }
     const GridState o = finalize_state(g, mx, mn, bad != 0.0, dt_hyp, mode, smax);
     if (coef_rows && mode == 0 && g.scheme == 0 && o.s >= 2 && o.s <= smax) {
-        for (int j = threadIdx.x; j <= o.s; j += 64) {
+        for (int j = l; j <= o.s; j += 64) {
             double r[5];
             rkl2_row(o.s, j, r);
             for (int i = 0; i < 5; ++i) coef_rows[5 * j + i] = r[i];
         }
     }
-    if (threadIdx.x != 0) return;
+    if (l != 0) return;
     *st = o;
     if (s_out) *s_out = o.s;
+    if (ext_ok) *ext_ok = 0;
 }
 
 hipError_t launch_finalize(const double* partials, int nblocks, const GridConst& gc, double dt_hyp,
                            int mode, GridState* state, int32_t* s_out, int smax, hipStream_t st,
-                           double* coef_rows) {
-    finalize_kernel<<<1, 64, 0, st>>>(partials, nblocks, gc, dt_hyp, mode, state, s_out, smax, coef_rows);
+                           double* coef_rows, const double* ext_part, int ext_nb, int32_t* ext_ok) {
+    finalize_kernel<<<1, kFinThreads, 0, st>>>(partials, nblocks, gc, dt_hyp, mode, state, s_out, smax, coef_rows,
+                                               ext_part, ext_nb, ext_ok);
     return hipGetLastError();
 }
 
@@ -117,10 +147,16 @@ static hipError_t launch_prec(const StageLaunch& P, int nblocks, int bx, int by,
     return hipErrorInvalidValue;
 }
 
+int64_t stage_blocks(Variant v, const GridConst& gc) {
+    if (gc.fixed) v = Variant{16, 16, v.bz, 1};
+    return (int64_t)((gc.n0 + v.bx - 1) / v.bx) * ((gc.n1 + v.by - 1) / v.by) * ((gc.n2 + v.bz - 1) / v.bz);
+}
+
 hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind, int stage,
                         const double* Yin, const double* Ym2, const double* Y0, const void* MY0in,
                         void* MY0out, double* Yout, const void* b, const GridState* state,
-                        const double* coef, hipStream_t st, double sub_scale, const Route* route) {
+                        const double* coef, hipStream_t st, double sub_scale, const Route* route,
+                        const ExtOut* ext) {
     if (gc.fixed) v = Variant{16, 16, v.bz, 1};   // the tile shape of the ghost-loading kernel
     StageLaunch P;
     TileArgs& a = P.t;
@@ -147,6 +183,7 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
     a.ih2 = gc.ih2;
     a.scale = 0.0;
     a.mu = a.nu = a.omn = a.mut = a.gt = 0.0;
+    a.ext = 0;
     P.ntx = (gc.n0 + v.bx - 1) / v.bx;
     P.nty = (gc.n1 + v.by - 1) / v.by;
     P.bz = v.bz;
@@ -162,6 +199,12 @@ hipError_t launch_stage(int precision, Variant v, const GridConst& gc, int kind,
     P.fac = gc.fac;
     P.sub_scale = sub_scale;
     P.route = Route{nullptr, nullptr, 0, 0};
+    P.ext = ExtOut{nullptr, nullptr};
+    if (ext) {
+        // the last-stage extrema: routed RKL2 stages of 3-D grids without fixed axes
+        if (!route || kind != 2 || gc.ndim != 3 || gc.fixed || !ext->part || !ext->ok) return hipErrorInvalidValue;
+        P.ext = *ext;
+    }
     if (route) {
         // routed stages: Yout carries the caller's T to the kernel
         if ((kind != 1 && kind != 2) || !route->A || !route->B || !Yout) return hipErrorInvalidValue;

@@ -20,6 +20,7 @@ struct StageLaunch {
     double fac;
     double sub_scale;    // kind 3: -tau_sub (gamma-1)/rho
     Route route;         // route.A != NULL: Yin, Ym2, Yout chosen on the device (kinds 1, 2)
+    ExtOut ext;          // ext.part != NULL: the launch of stage j = s keeps the extrema of Y_s
 };
 
 // MODE 1: 3-D grid, tile shape fixed at compile time (run_tile's CBX, CBY);
@@ -65,6 +66,7 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
                 a.Ym2 = j == 2 ? T : Yj;   // Y_{j-2} sits where Y_j goes
             }
             a.Yout = j == s ? T : Yj;
+            a.ext = MODE == 1 && P.ext.part && j == s;
         }
         const double* cf = P.coef + 5 * (P.route.coef_flat ? (size_t)P.stage : (size_t)s * (s + 1) / 2 + P.stage);
         a.mu = cf[0];
@@ -75,9 +77,40 @@ __global__ __launch_bounds__(BX* BY) void stage_kernel(StageLaunch P) {
         a.scale = -st->cdiv;
     }
     const FaceK<R> fk = make_facek<R>(P.kappa0, P.kexp, P.kperp, P.satq, tref);
-    if constexpr (MODE == 1)
-        run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), BX, BY, false, 6, true>(a, fk, tref, L);
-    else if constexpr (MODE == 2)
+    if constexpr (MODE == 1) {
+        const TileExt e =
+            run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), BX, BY, false, 6, true>(a, fk, tref, L);
+        if (a.ext) {   // uniform: the last stage of a routed sequence
+            // the workgroup's extrema of Y_s, as one block of the reduction pass
+            double mx = e.mx, mn = e.mn, bad = e.bad;
+            for (int off = 32; off > 0; off >>= 1) {
+                mx = fmax(mx, __shfl_xor(mx, off));
+                mn = fmin(mn, __shfl_xor(mn, off));
+                bad = fmax(bad, __shfl_xor(bad, off));
+            }
+            constexpr int NW = BX * BY / 64;
+            __shared__ double esm[3][NW];
+            const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+            if (l == 0) {
+                esm[0][w] = mx;
+                esm[1][w] = mn;
+                esm[2][w] = bad;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int i = 1; i < NW; ++i) {
+                    mx = fmax(mx, esm[0][i]);
+                    mn = fmin(mn, esm[1][i]);
+                    bad = fmax(bad, esm[2][i]);
+                }
+                double* o = P.ext.part + 3 * (size_t)blockIdx.x;
+                o[0] = mx;
+                o[1] = mn;
+                o[2] = bad;
+                if (blockIdx.x == 0) *P.ext.ok = 1;   // read after this launch ends
+            }
+        }
+    } else if constexpr (MODE == 2)
         run_tile<R, LIM, SAT, KM, PL, (BX + 1) * BY, BX*(BY + 1), 0, 0, true>(a, fk, tref, L);
     else
         run_tile<R, LIM, SAT, KM>(a, fk, tref, L);

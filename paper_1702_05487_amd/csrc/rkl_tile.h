@@ -197,6 +197,13 @@ struct TileArgs {
     double ih0, ih1, ih2;
     double scale;        // multiplies div F: -(gamma-1)/rho (kind 0) or -tau (gamma-1)/rho
     double mu, nu, omn, mut, gt;
+    int ext;             // kind 2, compile-time tile shapes: keep the extrema of the stored output
+};
+
+// per-thread maximum, minimum and non-finite flag (0 or 1) of the stored
+// stage output (TileArgs::ext)
+struct TileExt {
+    double mx, mn, bad;
 };
 
 template <typename R, int PLMAX, int FXMAX, int FYMAX>
@@ -297,8 +304,8 @@ __device__ __forceinline__ double stage_combine(double mu, double nu, double omn
 // Neither changes a value.
 template <typename R, bool LIM, int SAT, int KM, int PLMAX, int FXMAX, int FYMAX, int CBX = 0, int CBY = 0,
           bool GH = false, int UNR = 1, bool NT = false>
-__device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, double tref,
-                                         TileLds<R, PLMAX, FXMAX, FYMAX>& L) {
+__device__ __forceinline__ TileExt run_tile(const TileArgs& a, const FaceK<R>& fk, double tref,
+                                            TileLds<R, PLMAX, FXMAX, FYMAX>& L) {
     constexpr bool FIX = CBX > 0;
     static_assert(!FIX || (2 * CBX + 2 * CBY + 4 <= CBX * CBY && CBX + CBY <= CBX * CBY),
                   "the ring cells and extra faces need one thread each");
@@ -380,7 +387,9 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
         return gon ? ghost_T(g, a.Yin, k, n2, oz, fz, xy, (size_t)plane) : pp[xy];
     };
 
+    TileExt ex{-INFINITY, INFINITY, 0.0};
     if constexpr (UNR == 6) {
+        const bool ext_on = a.ext != 0;
         // Register rings.  The value for plane k + m sits in slot (P + m) mod L
         // of a ring of length L, P = (k - z0 + 2) mod 6.  The loop is unrolled
         // six-fold (every L divides six) with P a compile-time constant, so each
@@ -580,6 +589,12 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
                                                    (double)qmy0[r0]);
                     if constexpr (NT) __builtin_nontemporal_store(y, a.Yout + o);
                     else a.Yout[o] = y;
+                    if (ext_on) {
+                        // as the reduction pass over T does it
+                        ex.mx = fmax(ex.mx, y);
+                        ex.mn = fmin(ex.mn, y);
+                        ex.bad = isfinite(y) ? ex.bad : 1.0;
+                    }
                 }
             }
         };
@@ -789,6 +804,7 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, const FaceK<R>& fk, 
             fb ^= 1;
         }
     }
+    return ex;
 }
 
 }  // namespace rkl

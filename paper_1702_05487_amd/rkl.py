@@ -25,7 +25,7 @@ RKL_FLAG_NONPOS, RKL_FLAG_NONFINITE, RKL_FLAG_STAGES, RKL_FLAG_ABORTED = 1, 2, 4
 
 EXPORTS = [
     "rkl_plan", "rkl_destroy", "rkl_grid_offset", "rkl_set_ghosts", "rkl_flux_div", "rkl_dt_par",
-    "rkl_superstep", "rkl_superstep_async", "rkl_superstep_noalloc", "rkl_superstep_batched", "rkl_graph_capture", "rkl_graph_launch",
+    "rkl_superstep", "rkl_superstep_async", "rkl_supersteps_async", "rkl_superstep_noalloc", "rkl_superstep_batched", "rkl_graph_capture", "rkl_graph_launch",
     "rkl_query", "rkl_variant_count", "rkl_variant_info", "rkl_set_variant", "rkl_last_error",
     "rkl_profile", "rkl_profile_read", "rkl_autotune",
     "rkl_batch_policy_count", "rkl_batch_policy_info", "rkl_set_batch_policy", "rkl_autotune_batched",
@@ -92,6 +92,7 @@ def load(build_if_missing: bool = True):
         "rkl_dt_par": (i32, [vp, i32, vp, P(dbl), vp]),
         "rkl_superstep": (i32, [vp, i32, vp, vp, dbl, P(i32), vp]),
         "rkl_superstep_async": (i32, [vp, i32, vp, vp, dbl, i32, vp, vp]),
+        "rkl_supersteps_async": (i32, [vp, i32, vp, vp, dbl, i32, i32, vp, vp]),
         "rkl_superstep_noalloc": (i32, [P(rkl_grid_desc), i32, vp, vp, dbl, i32, vp, vp]),
         "rkl_superstep_batched": (i32, [vp, vp, vp, vp, vp, vp]),
         "rkl_graph_capture": (i32, [vp, vp, vp, vp, vp, vp]),
@@ -161,6 +162,11 @@ def rkl_superstep(plan, grid, T_ptr, b_ptr, dt_hyp, stream):
 
 def rkl_superstep_async(plan, grid, T_ptr, b_ptr, dt_hyp, s_cap, s_ptr, stream):
     _check(load().rkl_superstep_async(plan, grid, T_ptr, b_ptr, float(dt_hyp), int(s_cap), s_ptr, stream))
+
+
+def rkl_supersteps_async(plan, grid, T_ptr, b_ptr, dt_hyp, nsteps, s_cap, s_ptr, stream):
+    _check(load().rkl_supersteps_async(plan, grid, T_ptr, b_ptr, float(dt_hyp), int(nsteps), int(s_cap), s_ptr,
+                                       stream))
 
 
 NOALLOC_MAX_CELLS = 2097152
@@ -392,6 +398,16 @@ class Plan:
         tp, bp = self._tb(grid, T, b)
         sp = None if s_out is None else _dev_ptr(s_out, torch.int32, 1, "s_out")
         rkl_superstep_async(self.handle, grid, tp, bp, dt_hyp, s_cap, sp, _stream())
+
+    def supersteps_async(self, T, b, dt_hyp, nsteps, s_cap, s_out=None, grid=0):
+        """nsteps super-steps one after another without host synchronisation
+        (each super-step after the first takes the extrema its predecessor's
+        last stage kept); the stage counts land in the int32 device tensor
+        s_out of nsteps entries."""
+        import torch
+        tp, bp = self._tb(grid, T, b)
+        sp = None if s_out is None else _dev_ptr(s_out, torch.int32, int(nsteps), "s_out")
+        rkl_supersteps_async(self.handle, grid, tp, bp, dt_hyp, nsteps, s_cap, sp, _stream())
 
     def subcycle(self, T, b, dt_hyp, max_sub=1 << 20, grid=0):
         """Explicit sub-cycling over dt_hyp (T in place); returns the number of sub-steps."""
