@@ -159,3 +159,44 @@ def test_refusals(torch_cuda):
         with pytest.raises(rkl.RklError):
             plan.supersteps_async(Tg, bg, 1e-3, nsteps, cap)
     plan.close()
+
+
+def test_in_a_captured_graph(torch_cuda):
+    """captured once (three super-steps), replayed four times with eager
+    library work between the replays; each replay equals three eager
+    super-steps, so the kept extrema work across replays too"""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    n = (48, 40, 24)
+    h = tuple(1.0 / v for v in n)
+    T0, b = fields(n, 9)
+    p = dict(inputs.SPITZER_MC_SAT, kperp_ratio=0.01)
+    plan = rkl.Plan([lib_desc(n, h, 3, p)], precision="mixed", smax=64)
+    ref_plan = rkl.Plan([lib_desc(n, h, 3, p)], precision="mixed", smax=64)
+    T = torch.from_numpy(T0.copy()).to("cuda:0")
+    bg = torch.from_numpy(b.astype(np.float32)).to("cuda:0")
+    dt = inputs.midpoint_ratio(10) * plan.dt_par(T)
+    s_dev = torch.zeros(3, dtype=torch.int32, device="cuda:0")
+    Tref = T.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.supersteps_async(T, bg, dt, 3, 14, s_out=s_dev)   # warm-up outside the graph
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(3):
+        ref_plan.superstep(Tref, bg, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(T, Tref)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.supersteps_async(T, bg, dt, 3, 14, s_out=s_dev)
+    for rep in range(4):
+        graph.replay()
+        ss = []
+        for _ in range(3):
+            ss.append(ref_plan.superstep(Tref, bg, dt))      # eager work between the replays
+        torch.cuda.synchronize()
+        assert torch.equal(T, Tref), rep
+        assert s_dev.cpu().tolist() == ss, (rep, s_dev.cpu().tolist(), ss)
+    plan.close()
+    ref_plan.close()
