@@ -76,3 +76,67 @@ def test_full_size_mixed_superstep_every_cell(name):
           "(oracle %.0f s)" % (name, got.size, s, s_ref, err, linf, chg, sec), flush=True)
     assert s == s_ref
     assert err <= 1e-5
+
+
+def _window_t(torch, t, center, r):
+    """periodic window of half-width r of a [n2][n1][n0] (or (3, ...)) torch
+    tensor, copied to the host as float64"""
+    lead = t.dim() - 3
+    a = t
+    for ax, c in enumerate(center):
+        idx = torch.arange(c - r, c + r + 1, device=t.device) % t.shape[lead + ax]
+        a = a.index_select(lead + ax, idx)
+    return a.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name,precision", [("saturated_512", "mixed"), ("fused_768", "mixed"),
+                                            ("fused_768", "fp64")])
+def test_full_size_two_supersteps_sampled(name, precision):
+    """Super-steps 1 and 2 of the full-size workload (the second starts from
+    the library's own first result, with its own s) against the oracle at
+    sampled cells: periodic windows of half-width s1 + s2 + 1 hold the
+    centre's whole dependency cone over both super-steps, which the oracle
+    advances with the library's s1, s2 and the same dt_hyp.  Bars as for
+    one super-step: mixed max |diff| <= 1e-6 and rel-L1 of the change <=
+    1e-5; FP64 max |diff| <= 1e-12 |T|."""
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_1702_05487_amd import rkl
+    rkl.load(build_if_missing=False)
+    w = getattr(inputs, name)(fields=False)
+    T0 = inputs.noisy_temperature(w.n, 2, device="cuda:0")
+    b = inputs.tangled_b(w.n, 1, device="cuda:0")
+    b = b.float() if precision == "mixed" else b.double()
+    plan = rkl.Plan([lib_desc(w.n, w.h, 3, w.params)], precision=precision)
+    dt = w.ratio * plan.dt_par(T0)
+    T = T0.clone()
+    s1 = plan.superstep(T, b, dt)
+    s2 = plan.superstep(T, b, dt)
+    plan.close()
+    rng = np.random.default_rng(29)
+    n = w.n[0]
+    centers = [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(5)] + [(0, n - 1, 0), (n - 1, 0, n - 1)]
+    idx = tuple(torch.tensor(np.array(centers).T, device="cuda:0"))
+    got = T[idx].cpu().numpy()
+    t0 = T0[idx].cpu().numpy()
+    del T
+    oracle.set_threads(16)
+    r = s1 + s2 + 1
+    ref = []
+    t_start = time.time()
+    for c in centers:
+        win = oracle.Grid(n=(2 * r + 1,) * 3, h=tuple(w.h), ndim=3, **w.params)
+        bw = _window_t(torch, b, c, r)
+        Y1 = oracle.rkl2_fixed(win, _window_t(torch, T0, c, r), bw, s1, dt)
+        ref.append(oracle.rkl2_fixed(win, Y1, bw, s2, dt)[r, r, r])
+        print("  %s: centre %s done, %.0f s" % (name, c, time.time() - t_start), flush=True)
+    oracle.set_threads(1)
+    ref = np.array(ref)
+    err = np.abs(got - ref).max()
+    chg = rel_l1(got - t0, ref - t0)
+    print("%s %s, super-steps 1-2 (s %d, %d), %d sampled cells: max |diff| %.3e, rel-L1 of the change %.3e"
+          % (name, precision, s1, s2, len(centers), err, chg), flush=True)
+    if precision == "mixed":
+        assert err <= 1e-6 and chg <= 1e-5
+    else:
+        assert err <= 1e-12 * np.abs(ref).max()
