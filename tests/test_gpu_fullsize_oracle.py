@@ -1,9 +1,12 @@
-"""One full-size super-step of the 512^3 and 768^3 saturated workloads in
-mixed precision against the oracle at every cell (opt-in: set
-RKL_FULLSIZE_ORACLE=1; the oracle needs about 2 and 11 minutes on 16 host
-threads and ~40 GB of host memory at 768^3, so the default GPU run checks
-these sizes at sampled cells instead, in test_gpu_parity.py and
-test_gpu_fused.py).
+"""Full-size workloads against the oracle.
+
+One super-step of the 512^3 and 768^3 saturated workloads in mixed
+precision at every cell (opt-in: set RKL_FULLSIZE_ORACLE=1; the oracle
+needs about 2 and 11 minutes on 16 host threads and ~40 GB of host memory
+at 768^3, so the default GPU run checks these sizes at sampled cells
+instead, in test_gpu_parity.py and test_gpu_fused.py).  Super-steps 1 and
+2 at sampled cells: the 768^3 mixed workload in every GPU run (about 45 s
+of oracle work), the others opt-in.
 
 The oracle is fed the FP32-rounded unit vectors, so only the arithmetic
 differs; bars as for every mixed super-step: rel-L1 <= 1e-5, identical
@@ -21,9 +24,9 @@ import oracle
 from helpers import lib_desc, rel_l1
 from paper_1702_05487_amd import inputs
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get("RKL_FULLSIZE_ORACLE") != "1",
-                                 reason="opt-in full-size oracle run (RKL_FULLSIZE_ORACLE=1)")]
+pytestmark = pytest.mark.gpu
+optin = pytest.mark.skipif(os.environ.get("RKL_FULLSIZE_ORACLE") != "1",
+                           reason="opt-in full-size oracle run (RKL_FULLSIZE_ORACLE=1)")
 
 
 def _oracle_with_progress(label, fn, *args):
@@ -43,6 +46,7 @@ def _oracle_with_progress(label, fn, *args):
         th.join()
 
 
+@optin
 @pytest.mark.parametrize("name", ["saturated_512", "fused_768"])
 def test_full_size_mixed_superstep_every_cell(name):
     import torch
@@ -89,8 +93,9 @@ def _window_t(torch, t, center, r):
     return a.double().cpu().numpy()
 
 
-@pytest.mark.parametrize("name,precision", [("saturated_512", "mixed"), ("fused_768", "mixed"),
-                                            ("fused_768", "fp64")])
+@pytest.mark.parametrize("name,precision", [pytest.param("saturated_512", "mixed", marks=optin),
+                                            ("fused_768", "mixed"),
+                                            pytest.param("fused_768", "fp64", marks=optin)])
 def test_full_size_two_supersteps_sampled(name, precision):
     """Super-steps 1 and 2 of the full-size workload (the second starts from
     the library's own first result, with its own s) against the oracle at
