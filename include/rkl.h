@@ -25,7 +25,10 @@
  *   - Fields are device pointers, C order [n2][n1][n0] (axis 0 fastest).
  *     T is double.  b (the unit vector b = B/|B|, one per cell) is three such
  *     arrays back to back (component-major, 3*N elements); it is double for
- *     RKL_FP64 plans and float for RKL_MIXED plans.
+ *     RKL_FP64 plans and float for RKL_MIXED plans.  b is not checked: its
+ *     length and finiteness are the caller's (a NaN in b gives a face flux
+ *     of zero under saturation and NaN without it, and the RKL_FLAG_*
+ *     bits, which describe T, do not report it).
  *   - The caller owns every pointer it passes; the plan owns its scratch.
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
  *     enqueued on it; entry points that must read a device result back say

@@ -147,6 +147,45 @@ def test_stage_cap_exceeded(torch_cuda):
     plan.close()
 
 
+@pytest.mark.parametrize("precision,variant", [("mixed", 3), ("fp64", 1)])
+def test_non_finite_extrema_from_the_last_stage(torch_cuda, precision, variant):
+    """A NaN in the starting T: the first super-step's reduction pass flags
+    it on both routes, and the stage recurrence keeps that cell NaN, so every
+    later super-step's extrema carry the flag too: from the last stage within
+    one rkl_supersteps_async call, from the reduction pass between single
+    calls.  Stage counts, dt_par, flags and every bit of T (NaN included)
+    must agree between the two routes."""
+    torch = torch_cuda
+    from paper_1702_05487_amd import rkl
+    n = (40, 33, 23)
+    T0, b = fields(n, 9)
+    T0[11, 20, 17] = np.nan
+    p = dict(inputs.SPITZER_MC_SAT, kperp_ratio=0.01)
+    h = tuple(1.0 / v for v in n)
+    bg = torch.from_numpy(b).to("cuda:0", torch.float32 if precision == "mixed" else torch.float64)
+    plans = [rkl.Plan([lib_desc(n, h, 3, p)], precision=precision, variant=variant) for _ in range(2)]
+    Ts = [torch.from_numpy(T0).to("cuda:0") for _ in range(2)]
+    dt = inputs.midpoint_ratio(6) * plans[0].dt_par(Ts[0])
+    s_one = torch.zeros(3, dtype=torch.int32, device="cuda:0")
+    flags_one = []
+    for i in range(3):
+        plans[0].superstep_async(Ts[0], bg, dt, 12, s_out=s_one[i:i + 1])
+        flags_one.append(plans[0].query()[2])
+    s_many = torch.zeros(3, dtype=torch.int32, device="cuda:0")
+    plans[1].supersteps_async(Ts[1], bg, dt, 3, 12, s_out=s_many)
+    torch.cuda.synchronize()
+    q = [pl.query() for pl in plans]
+    for pl in plans:
+        pl.close()
+    print(precision, "stages", s_one.tolist(), "flags per super-step", flags_one, "query", q, flush=True)
+    assert s_one.tolist() == s_many.tolist() and s_one.tolist()[0] == 6
+    assert all(f & rkl.RKL_FLAG_NONFINITE for f in flags_one)
+    assert q[0] == q[1]
+    a, c = (t.cpu().numpy() for t in Ts)
+    assert np.isnan(a[11, 20, 17]) and not np.isinf(a).any()
+    assert np.array_equal(a.view(np.int64), c.view(np.int64))
+
+
 def test_refusals(torch_cuda):
     torch = torch_cuda
     from paper_1702_05487_amd import rkl
